@@ -1,0 +1,162 @@
+"""Seeded synthetic inputs and the named workloads.
+
+This module holds no arithmetic of the method: it only draws initial
+densities, particle positions, chains and bonds, and records the parameter
+sets of the workloads.  Both the GPU path and the oracle receive the same
+arrays from here.
+
+Recipe (the paper's simulations are its own synthetic set-ups; there is no
+dataset):
+  * densities: rho_A, rho_B = 1 + 0.01 * (2U - 1), independent per site and
+    component, U uniform from numpy's Philox bit generator with the
+    workload's seed -- a slightly perturbed 50/50 mixture, the starting point
+    of spinodal decomposition;
+  * free particles: uniform in the box, rejected while closer than `min_dist`
+    to an earlier one (periodic minimum image);
+  * chains: random walks of fixed bond length 0.97 started at uniform points,
+    each new bead rejected while closer than `min_dist` to a bead already
+    placed that is not its bonded predecessor.
+"""
+import math
+
+import numpy as np
+
+WCA_CUT = 2.0 ** (1.0 / 6.0)
+
+# Parameter sets.  "shape" = (nx, ny, nz); G is the 2x2 coupling matrix.
+WORKLOADS = {
+    # 32^3 FP64, velocity-shift forcing, 64 free particles, friction only.
+    "c1": dict(shape=(32, 32, 32), precision="fp64", forcing="shift", tau=(1.0, 1.0),
+               G=((0.0, 1.6), (1.6, 0.0)), gamma=0.5, kT=0.0, seed=1,
+               kappa=((0.0, 0.0),), mass=(1.0,), charge=(0.0,),
+               particles=dict(kind="free", n=64, min_dist=0.0), wca=None, fene=None, dh=None,
+               steps=100),
+    # 128^3 FP32 spinodal decomposition with 20,000 solvated WCA particles.
+    "c2": dict(shape=(128, 128, 128), precision="fp32", forcing="paper", tau=(1.0, 1.0),
+               G=((0.0, 1.8), (1.8, 0.0)), gamma=1.0, kT=0.0, seed=2,
+               kappa=((0.05, 0.0),), mass=(100.0,), charge=(0.0,),
+               particles=dict(kind="free", n=20000, min_dist=WCA_CUT), wca=(1.0, 1.0), fene=None,
+               dh=None, steps=2000),
+    # 256^3 FP32 polyelectrolyte-like mixture: 2,000 chains x 100 beads,
+    # FENE + WCA + screened Debye-Hueckel, fluctuating fluid.
+    "c3": dict(shape=(256, 256, 256), precision="fp32", forcing="paper", tau=(1.0, 1.0),
+               G=((0.0, 1.8), (1.8, 0.0)), gamma=1.0, kT=1e-4, seed=3,
+               kappa=((0.1, 0.0),), mass=(2000.0,), charge=(1.0,),
+               particles=dict(kind="chains", nchains=2000, nbeads=100, bond=0.97, min_dist=0.9),
+               wca=(1.0, 1.0), fene=(30.0, 1.5), dh=(1.0, 3.0, 1.0), steps=1000),
+    # The 128^3 spinodal set-up at 256^3 (same particle number density:
+    # 160,000 particles), plain FP32 storage.
+    "c2_256": dict(shape=(256, 256, 256), precision="fp32", forcing="paper", tau=(1.0, 1.0),
+                   G=((0.0, 1.8), (1.8, 0.0)), gamma=1.0, kT=0.0, seed=6,
+                   kappa=((0.05, 0.0),), mass=(100.0,), charge=(0.0,),
+                   particles=dict(kind="free", n=160000, min_dist=WCA_CUT), wca=(1.0, 1.0),
+                   fene=None, dh=None, steps=200),
+}
+
+
+def rng(seed):
+    return np.random.Generator(np.random.Philox(seed))
+
+
+def initial_densities(shape, seed, amp=0.01, mean=1.0):
+    """[2][nz][ny][nx] float64: mean + amp*(2U-1) per site and component."""
+    nx, ny, nz = shape
+    g = rng(seed)
+    return mean + amp * (2.0 * g.random((2, nz, ny, nx)) - 1.0)
+
+
+def _too_close_grid(points, box, min_dist):
+    """Cell hash for rejection sampling; returns (insert, check) closures."""
+    cell = max(min_dist, 1e-9)
+    ncell = [max(1, int(math.floor(b / cell))) for b in box]
+    grid = {}
+
+    def key(p):
+        return tuple(int(math.floor(p[a] / box[a] * ncell[a])) % ncell[a] for a in range(3))
+
+    def insert(i, p):
+        grid.setdefault(key(p), []).append(i)
+
+    def check(p, ignore=()):
+        if min_dist <= 0.0:
+            return False
+        k = key(p)
+        rng_ = [range(-1, 2) if ncell[a] >= 3 else range(0, ncell[a]) for a in range(3)]
+        for dx in rng_[0]:
+            for dy in rng_[1]:
+                for dz in rng_[2]:
+                    kk = ((k[0] + dx) % ncell[0], (k[1] + dy) % ncell[1], (k[2] + dz) % ncell[2])
+                    for j in grid.get(kk, ()):
+                        if j in ignore:
+                            continue
+                        d = points[j] - p
+                        d -= np.asarray(box) * np.floor(d / np.asarray(box) + 0.5)
+                        if d @ d < min_dist * min_dist:
+                            return True
+        return False
+
+    return insert, check
+
+
+def free_particles(n, shape, seed, min_dist=0.0, max_tries=1000):
+    """n positions uniform in the periodic box [0,nx)x[0,ny)x[0,nz)."""
+    g = rng(seed + 1000003)
+    box = np.asarray(shape, dtype=np.float64)
+    if min_dist <= 0.0:
+        return g.random((n, 3)) * box
+    pts = np.zeros((n, 3))
+    insert, check = _too_close_grid(pts, box, min_dist)
+    for i in range(n):
+        for _ in range(max_tries):
+            p = g.random(3) * box
+            if not check(p):
+                break
+        else:
+            raise RuntimeError("could not place particle %d" % i)
+        pts[i] = p
+        insert(i, p)
+    return pts
+
+
+def chains(nchains, nbeads, shape, seed, bond=0.97, min_dist=0.9, max_tries=200):
+    """Random-walk chains.  Returns positions [nchains*nbeads][3] (wrapped into
+    the box) and bonds [nchains*(nbeads-1)][2] (int32)."""
+    g = rng(seed + 2000003)
+    box = np.asarray(shape, dtype=np.float64)
+    n = nchains * nbeads
+    pts = np.zeros((n, 3))
+    insert, check = _too_close_grid(pts, box, min_dist)
+    bonds = []
+    for c in range(nchains):
+        base = c * nbeads
+        for _ in range(max_tries):
+            p = g.random(3) * box
+            if not check(p):
+                break
+        pts[base] = p
+        insert(base, p)
+        for b in range(1, nbeads):
+            prev = pts[base + b - 1]
+            for _ in range(max_tries):
+                d = g.normal(size=3)
+                d *= bond / np.linalg.norm(d)
+                p = np.mod(prev + d, box)
+                if not check(p, ignore=(base + b - 1,)):
+                    break
+            pts[base + b] = p
+            insert(base + b, p)
+            bonds.append((base + b - 1, base + b))
+    return pts, np.asarray(bonds, dtype=np.int32).reshape(-1, 2)
+
+
+def particles_for(w, shape=None):
+    """Particles of workload dict `w` (optionally re-scaled to another box at
+    the same number density).  Returns (x, bonds or None)."""
+    shape = tuple(shape or w["shape"])
+    spec = w["particles"]
+    scale = np.prod(shape) / np.prod(w["shape"])
+    if spec["kind"] == "free":
+        n = int(round(spec["n"] * scale))
+        return free_particles(n, shape, w["seed"], spec["min_dist"]), None
+    nch = max(1, int(round(spec["nchains"] * scale)))
+    return chains(nch, spec["nbeads"], shape, w["seed"], spec["bond"], spec["min_dist"])
