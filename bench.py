@@ -1,0 +1,194 @@
+"""Throughput of the coupled Shan-Chen LB + particle step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2_256]
+
+Prints one JSON line.  A step is one pass of the whole path: particle half
+kick and drift, density and Shan-Chen force, coupling forces at the nodes,
+spread, collision with forcing (and fluctuations when kT > 0), streaming,
+second half kick and the FP64 conservation sums.  Inputs are resident on the
+device before the timed region starts.
+
+value            lattice updates per second (MLUPS) over the timed K steps
+roofline         the fused collide-stream kernel: algorithmic bytes per launch
+                 (38 populations read + 38 written per site) over its average
+                 launch duration, from HIP events on the stream it runs on
+cpu_baseline     the FP64 oracle on the host cores, on a 64^3 box of the same
+                 workload (same densities recipe, same particle number density)
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbmd_fluid.hip", "lbmd_site.h", "lbmd_internal.h"):
+        with open(os.path.join(ROOT, "paper_1306_0788_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, nsites, s_bytes):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(PROFILE_DIR, "k_fused_%s_counters.md" % workload)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel source hash:\s*([0-9a-f]+)", txt)
+    t = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
+def setup(workload, stream, kernel, tiling):
+    from paper_1306_0788_amd import lbmd, workloads
+    w = workloads.WORKLOADS[workload]
+    shape = w["shape"]
+    rho = workloads.initial_densities(shape, w["seed"]).reshape(2, -1)
+    x, bonds = workloads.particles_for(w)
+    prec = lbmd.FP32 if w["precision"] == "fp32" else lbmd.FP64
+    forcing = lbmd.FORCE_SHIFT if w["forcing"] == "shift" else lbmd.FORCE_PAPER
+    sim = lbmd.Sim(shape, precision=prec, forcing=forcing, kernel=kernel, tau=w["tau"], G=w["G"],
+                   gamma=w["gamma"], kappa=w["kappa"][0], mass=w["mass"][0], kT=w["kT"], seed=w["seed"],
+                   rho_init=rho, stream=stream)
+    sim.set_particle_types(w["kappa"], w["mass"], w["charge"])
+    if w["wca"]:
+        sim.set_pair_potential(lbmd.PAIR_WCA, w["wca"])
+    if w["dh"]:
+        sim.set_pair_potential(lbmd.PAIR_DH, w["dh"])
+    if w["fene"]:
+        sim.set_pair_potential(lbmd.BOND_FENE, w["fene"])
+    sim.set_particles(x)
+    if bonds is not None:
+        sim.set_bonds(bonds)
+    if tiling:
+        sim.set_tiling(*tiling)
+    return sim, w, len(x)
+
+
+def cpu_baseline(workload, target_s=15.0):
+    """The FP64 oracle as it stands, single thread, on a 64^3 box of the
+    same workload: MLUPS over as many steps as fit in about target_s."""
+    import oracle
+    from paper_1306_0788_amd import workloads
+    w = workloads.WORKLOADS[workload]
+    shape = (64, 64, 64)
+    rho = workloads.initial_densities(shape, w["seed"]).reshape(2, -1)
+    x, bonds = workloads.particles_for(w, shape)
+    P = oracle.make_params(shape, tau=w["tau"], G=w["G"],
+                           forcing=oracle.FORCE_SHIFT if w["forcing"] == "shift" else oracle.FORCE_PAPER,
+                           gamma=w["gamma"], kT=w["kT"], seed=w["seed"], kappa=w["kappa"], mass=w["mass"],
+                           charge=w["charge"], wca=w["wca"], fene=w["fene"], dh=w["dh"])
+    s = oracle.Sim(P, rho, x, None, None, bonds)
+    t0 = time.perf_counter()
+    s.step(1)
+    t1 = time.perf_counter()
+    n = max(1, int(target_s / max(t1 - t0, 1e-3)) - 1)
+    s.step(n)
+    t2 = time.perf_counter()
+    steps = n + 1
+    mlups = 64 ** 3 * steps / (t2 - t0) / 1e6
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "FP64 oracle, 1 thread, %d steps of a 64^3 box of workload %s (%d particles)"
+                      % (steps, workload, len(x))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2_256")
+    ap.add_argument("--kernel", choices=["fused", "twopass"], default="fused")
+    ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("TILE_Y", "TILE_Z"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (the path shards by z-slabs across GPUs, "
+              "which is not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1306_0788_amd import lbmd
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    # a dedicated stream (the current one may be the null stream, handle 0,
+    # which the library would replace by a stream of its own)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    kernel = lbmd.KERNEL_FUSED if args.kernel == "fused" else lbmd.KERNEL_TWOPASS
+    print("bench: setting up %s" % args.workload, file=sys.stderr, flush=True)
+    sim, w, npart = setup(args.workload, stream.cuda_stream, kernel, args.tiling)
+    N = int(np.prod(w["shape"]))
+    s_bytes = 4 if w["precision"] == "fp32" else 8
+
+    print("bench: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    assert sim.sync() == lbmd.OK, sim.last_error()
+
+    sim.kernel_timing(True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    sim.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    kms, launches = sim.kernel_timing(False)
+    st = sim.sync()
+    if st != lbmd.OK:
+        print("bench: numerical failure: %s" % sim.last_error(), file=sys.stderr)
+        sys.exit(1)
+    print("bench: timed %d steps in %.3f ms" % (args.steps, ms), file=sys.stderr, flush=True)
+
+    mlups = N * args.steps / (ms * 1e-3) / 1e6
+    alg_bytes = 76 * s_bytes * N
+    kavg_s = kms * 1e-3 / max(launches, 1)
+    achieved = alg_bytes / kavg_s / 1e9
+    traffic = measured_traffic(args.workload, N, s_bytes)
+    line = {
+        "metric": "MLUPS (2-component D3Q19 Shan-Chen + coupled particles, one full step)",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if s_bytes == 4 else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "lattice": list(w["shape"]), "particles": npart,
+                   "forcing": w["forcing"], "kT": w["kT"], "kernel": args.kernel,
+                   "particle_updates_per_s": round(npart * args.steps / (ms * 1e-3), 1)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_fused" if kernel == lbmd.KERNEL_FUSED else "k_collide",
+                     "kernel_ms_avg": round(kavg_s * 1e3, 5), "bytes_per_site": 76 * s_bytes},
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * lbmd -- two-component Shan-Chen lattice Boltzmann fluid coupled to
+ * off-lattice point particles, on one AMD MI355X (gfx950).
+ *
+ * Method: Sega, Sbragaglia, Kantorovich, Ivanov, arXiv 1306.0788.
+ *   fluid      Sec. 2 (Eqs. SCforce, LBMIX) and the Appendix (Eqs. feq,
+ *              weights, velo, collis, MODES, momentum_definition and the
+ *              forcing source term), D3Q19, periodic box, BGK relaxation
+ *              (every non-conserved mode relaxes with -1/tau);
+ *   particles  Sec. 2 (Eqs. NEWTON and solvation_kappa): friction against
+ *              the trilinearly interpolated fluid velocity, solvation force
+ *              -sum_zeta kappa_zeta grad rho_zeta, random force of variance
+ *              2 kT gamma, and the opposite force spread back onto the 8
+ *              surrounding nodes so that total momentum is conserved.
+ *
+ * Units: lattice spacing 1, time step 1 (the paper's tau is the time step;
+ * here tau[] is the BGK relaxation time of each component).
+ *
+ * Layouts (all host arrays are float64, C order):
+ *   site index   s = (z*ny + y)*nx + x, x fastest; N = nx*ny*nz
+ *   densities    [2][N]            component A then B
+ *   velocity     [3][N]            u_c = (j + g_SC/2)/rho, the velocity the
+ *                                  particles see (Appendix, u definition)
+ *   populations  [2][19][N]        post-streaming populations f_zeta,i(s) in
+ *                                  the velocity order: 0 rest; 1..6 = +x,-x,
+ *                                  +y,-y,+z,-z; 7..18 = (+,+,0),(-,-,0),
+ *                                  (+,-,0),(-,+,0),(+,0,+),(-,0,-),(+,0,-),
+ *                                  (-,0,+),(0,+,+),(0,-,-),(0,+,-),(0,-,+)
+ *   particles    [n][3]            positions in [0,L) per axis, velocities,
+ *                                  forces
+ *
+ * Ownership: the library owns all device memory it allocates (hipMalloc).
+ * Host arrays passed in are copied before the call returns; the caller keeps
+ * them.  Output arrays belong to the caller.
+ *
+ * Errors: every call returns LBMD_OK (0) or a negative code.  Parameter
+ * errors are reported synchronously and leave the handle unchanged.  A
+ * numerical failure (a density <= 0 or a non-finite density, momentum or
+ * particle quantity -- Sec. 3: negative densities mean failure of the
+ * Shan-Chen scheme) is latched on the device and returned as
+ * LBMD_EUNSTABLE by the next lbmd_sync / lbmd_get_* / lbmd_reductions call
+ * (and by lbmd_step when check_every > 0); lbmd_last_error names the first
+ * failing step.  Once latched, the state stays readable but further
+ * lbmd_step calls return LBMD_ESTATE.
+ *
+ * Threading: one handle = one HIP stream; calls on one handle must not
+ * overlap.  Different handles are independent.
+ */
+#ifndef LBMD_H
+#define LBMD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbmd_ctx* lbmd_handle;
+
+#define LBMD_OK 0
+#define LBMD_EINVAL (-1)    /* invalid argument                         */
+#define LBMD_ENOMEM (-2)    /* device allocation failed                 */
+#define LBMD_EDEVICE (-3)   /* HIP runtime error                        */
+#define LBMD_EUNSTABLE (-4) /* numerical failure latched on the device  */
+#define LBMD_ESTATE (-5)    /* call not valid in the handle's state     */
+
+/* storage precision of the populations (arithmetic is done in the same type) */
+#define LBMD_FP64 0
+#define LBMD_FP32 1
+
+/* forcing scheme */
+#define LBMD_FORCE_PAPER 0 /* Appendix forcing source term with the half-force
+                              barycentric velocity; needs tau[0] == tau[1]   */
+#define LBMD_FORCE_SHIFT 1 /* Shan-Chen velocity shift of the equilibrium
+                              velocity (u' + tau_zeta g_zeta / rho_zeta); kT
+                              must be 0                                       */
+
+/* fluid kernel organisation (same results up to rounding order) */
+#define LBMD_KERNEL_FUSED 0   /* one pass: density halo in LDS + collide +
+                                 stream, then a sparse fix-up at the nodes the
+                                 particles touch                              */
+#define LBMD_KERNEL_TWOPASS 1 /* density pass, then collide + stream          */
+
+/* lbmd_get_fields masks; outputs are concatenated in this order */
+#define LBMD_RHO 1u /* [2][N] */
+#define LBMD_U 2u   /* [3][N] */
+#define LBMD_POP 4u /* [2][19][N] */
+
+/* pair potentials for lbmd_set_pair_potential */
+#define LBMD_PAIR_WCA 0  /* params {sigma, eps}: 4 eps[(s/r)^12-(s/r)^6]+eps,
+                            r < 2^(1/6) sigma                                 */
+#define LBMD_PAIR_DH 1   /* params {kappa_D, r_c, l_B}: q_i q_j l_B e^{-kappa r}
+                            / r, r < r_c                                       */
+#define LBMD_BOND_FENE 2 /* params {k, R0}: -k R0^2/2 ln(1-(r/R0)^2) on bonds */
+
+#define LBMD_MAX_TYPES 8
+
+typedef struct {
+  int32_t nx, ny, nz;  /* periodic lattice, each >= 1                       */
+  int32_t precision;   /* LBMD_FP64 or LBMD_FP32                            */
+  int32_t forcing;     /* LBMD_FORCE_PAPER or LBMD_FORCE_SHIFT              */
+  int32_t kernel;      /* LBMD_KERNEL_FUSED or LBMD_KERNEL_TWOPASS          */
+  double tau[2];       /* BGK relaxation time per component, > 1/2          */
+  double G[2][2];      /* coupling g_{zeta zeta'} of the Shan-Chen force
+                          (Sec. 2, Eq. SCforce) with psi = rho; G[0][1] ==
+                          G[1][0] conserves momentum                         */
+  double gamma;        /* particle friction (Eq. NEWTON)                    */
+  double kappa[2];     /* solvation kappa_A, kappa_B of particle type 0
+                          (Eq. solvation_kappa)                             */
+  double mass;         /* particle mass of type 0 (> 0)                     */
+  double kT;           /* thermal energy; 0 = deterministic                 */
+  uint64_t seed;       /* Philox4x32-10 key for fluid and particle noise    */
+  int32_t check_every; /* lbmd_step polls the status word every this many
+                          steps (0 = never; errors surface at sync/get)     */
+  int32_t reserved;    /* must be 0                                         */
+} lbmd_params;
+
+/* Create a simulation.  rho_init: host [2][N] initial densities, or NULL for
+   1.0 everywhere; the fluid starts at rest, f = w_i rho_zeta (Appendix,
+   Eq. feq with u = 0).  hip_stream: a hipStream_t to run on (e.g. torch's
+   current stream), or NULL for a stream owned by the library.  On success
+   *out receives the handle.  Errors: LBMD_EINVAL (bad parameters, tau <= 1/2,
+   unequal tau with LBMD_FORCE_PAPER, kT > 0 with LBMD_FORCE_SHIFT, kT < 0),
+   LBMD_ENOMEM, LBMD_EDEVICE. */
+int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, lbmd_handle* out);
+
+/* Free every device allocation of the handle (waits for its stream). */
+int lbmd_destroy(lbmd_handle h);
+
+/* Replace the particles (Sec. 2, Eq. NEWTON).  pos: host [n][3] (wrapped into
+   the box); vel: host [n][3] or NULL (zero); type: host [n] in [0, ntypes)
+   or NULL (type 0).  Forces from the previous step are reset to zero.
+   n = 0 removes all particles.  Errors: LBMD_EINVAL (non-finite values, bad
+   type), LBMD_ENOMEM. */
+int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double* vel,
+                       const int32_t* type);
+
+/* Per-type solvation constants kappa [ntypes][2] (Eq. solvation_kappa), masses
+   [ntypes] (> 0) and charges [ntypes] (NULL = 0), ntypes <= LBMD_MAX_TYPES.
+   Type 0 initially takes kappa/mass from lbmd_params. */
+int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, const double* mass,
+                            const double* charge);
+
+/* Switch a conservative particle interaction on (params != NULL) or off
+   (params == NULL).  The WCA form is the one the paper uses for excluded
+   volume, with the usual +eps shift; the screened Debye-Hueckel form is the
+   paper's short-range electrostatics.  Cut-offs must be below half the
+   smallest box edge.  Errors: LBMD_EINVAL. */
+int lbmd_set_pair_potential(lbmd_handle h, int32_t kind, const double* params);
+
+/* FENE bonds: pairs [nb][2] of particle indices (host, copied).  Each
+   particle may take part in at most 8 bonds.  Errors: LBMD_EINVAL. */
+int lbmd_set_bonds(lbmd_handle h, int64_t nb, const int32_t* pairs);
+
+/* Enqueue nsteps time steps on the handle's stream and return (asynchronous
+   unless check_every > 0).  Each step: particle half kick and drift, fluid
+   moments and Shan-Chen force, coupling forces at the new positions, the
+   opposite force spread onto the nodes, collision with forcing (and noise if
+   kT > 0), streaming, second half kick.  Errors: LBMD_ESTATE after a
+   latched failure, LBMD_EUNSTABLE when a poll finds one, LBMD_EDEVICE. */
+int lbmd_step(lbmd_handle h, int64_t nsteps);
+
+/* Wait for the handle's stream; returns the latched status. */
+int lbmd_sync(lbmd_handle h);
+
+/* Write the fields selected by mask (LBMD_RHO | LBMD_U | LBMD_POP) of the
+   current state, concatenated in that order, as float64 into out: a host
+   pointer (out_is_device = 0; the call waits) or a device pointer on the same
+   device (out_is_device = 1; enqueued on the handle's stream).  u needs the
+   Shan-Chen force and so reads the density halo.  Returns the latched
+   status. */
+int lbmd_get_fields(lbmd_handle h, uint32_t mask, double* out, int32_t out_is_device);
+
+/* Host copies of the particle state (any pointer may be NULL): positions,
+   velocities, total forces F(n) and their coupling part (friction +
+   solvation + random), each [n][3].  Waits.  Returns the latched status. */
+int lbmd_get_particles(lbmd_handle h, double* pos, double* vel, double* force, double* fcoup);
+
+/* Replace the populations with host [2][19][N] post-streaming values
+   (resume, fault injection).  Errors: LBMD_EINVAL on a NULL pointer. */
+int lbmd_set_populations(lbmd_handle h, const double* pop);
+
+/* Conservation sums of the state at the start of the most recent step, in
+   float64: out[0..1] = sum rho_A, sum rho_B; out[2..4] = raw fluid momentum
+   sum_zeta,i f c_i; out[5..7] = sum_p (m v_p + F_coup,p / 2).  With a
+   symmetric G and a force-free box out[2..4] + out[5..7] is conserved
+   exactly (up to rounding).  *step_out (may be NULL) receives the index of
+   that step, -1 before the first step.  Waits.  Returns the latched status. */
+int lbmd_reductions(lbmd_handle h, double* out, int64_t* step_out);
+
+/* Number of steps taken so far. */
+int64_t lbmd_get_step(lbmd_handle h);
+
+/* Message of the last error on the handle (static storage of the handle). */
+const char* lbmd_last_error(lbmd_handle h);
+
+/* Launch configuration of the fused fluid kernel: z planes marched per block
+   (tile_z >= 1) and rows per block (tile_y in {2, 4, 8, 16}).  Same results;
+   only speed changes.  Errors: LBMD_EINVAL. */
+int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z);
+
+/* Timing of the collide-stream kernel (the fused kernel, or the collide
+   kernel of the two-pass organisation): enable = 1 clears the record and
+   brackets every later launch with HIP events on the handle's stream;
+   enable = 0 stops.  Either way *total_ms (may be NULL) receives the summed
+   duration of the recorded launches and *launches (may be NULL) their
+   number.  Waits.  Errors: LBMD_EDEVICE. */
+int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -129,6 +129,9 @@ def lib():
         L.orc_site_collide.argtypes = [_PP, ctypes.c_int64, _D, ctypes.c_int64, _D, _D]
         L.orc_site_collide.restype = ctypes.c_int
         L.orc_node_fields.argtypes = [_PP, _D, ctypes.c_int64, _D, _D]
+        L.orc_coupling_force_one.argtypes = [_PP, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, ctypes.c_int64, _D]
+        L.orc_particle_force_at.argtypes = [_PP, ctypes.c_int64, _D, ctypes.c_int64, _D, _D, _I32,
+                                            ctypes.c_int64, _D]
         _lib = L
     return _lib
 
@@ -275,6 +278,23 @@ def node_fields(P, f, site):
     grad = np.zeros((2, 3))
     lib().orc_node_fields(ctypes.byref(P), _dp(f), site, _dp(uc), _dp(grad))
     return uc, grad
+
+
+def coupling_force_one(P, step, f, xp, vp, type_, p):
+    Fc = np.zeros(3)
+    lib().orc_coupling_force_one(ctypes.byref(P), step, _dp(_c64(f)), _dp(_c64(xp)), _dp(_c64(vp)), int(type_),
+                                 int(p), _dp(Fc))
+    return Fc
+
+
+def particle_force_at(P, step, f, x, v, type_, site):
+    """-sum_p W_p(site) F_coup,p (positions/velocities after the half kick and drift)."""
+    gP = np.zeros(3)
+    x, v = _c64(x), _c64(v)
+    t = np.ascontiguousarray(type_, np.int32)
+    lib().orc_particle_force_at(ctypes.byref(P), step, _dp(_c64(f)), x.shape[0], _dp(x), _dp(v),
+                                t.ctypes.data_as(_I32), int(site), _dp(gP))
+    return gP
 
 
 class Sim:

@@ -501,6 +501,44 @@ void orc_node_fields(const orc_params* P, const double* f, int64_t site, double*
   }
 }
 
+void orc_coupling_force_one(const orc_params* P, int64_t step, const double* f, const double* xp,
+                            const double* vp, int32_t type, int64_t p, double* Fc) {
+  int64_t node[8];
+  double W[8], up[3] = {0, 0, 0}, gr[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  orc_interp_weights(xp, P->nx, P->ny, P->nz, node, W);
+  for (int k = 0; k < 8; k++) {
+    double uc[3], grad[6];
+    orc_node_fields(P, f, node[k], uc, grad);
+    for (int a = 0; a < 3; a++) {
+      up[a] += W[k] * uc[a];
+      for (int c = 0; c < 2; c++) gr[c][a] += W[k] * grad[3 * c + a];
+    }
+  }
+  double R[4] = {0, 0, 0, 0};
+  if (P->kT > 0.0) {
+    orc_site_normals(P->seed, step, p, 1, 1, R);
+    for (int a = 0; a < 3; a++) R[a] *= sqrt(2.0 * P->kT * P->gamma);
+  }
+  for (int a = 0; a < 3; a++)
+    Fc[a] = -P->gamma * (vp[a] - up[a]) - (P->kappa[type][0] * gr[0][a] + P->kappa[type][1] * gr[1][a]) + R[a];
+}
+
+void orc_particle_force_at(const orc_params* P, int64_t step, const double* f, int64_t np, const double* x,
+                           const double* v, const int32_t* type, int64_t site, double* gP) {
+  gP[0] = gP[1] = gP[2] = 0.0;
+  for (int64_t p = 0; p < np; p++) {
+    int64_t node[8];
+    double W[8];
+    orc_interp_weights(&x[3 * p], P->nx, P->ny, P->nz, node, W);
+    for (int k = 0; k < 8; k++) {
+      if (node[k] != site) continue;
+      double Fc[3];
+      orc_coupling_force_one(P, step, f, &x[3 * p], &v[3 * p], type ? type[p] : 0, p, Fc);
+      for (int a = 0; a < 3; a++) gP[a] -= W[k] * Fc[a];
+    }
+  }
+}
+
 int orc_site_collide(const orc_params* P, int64_t step, const double* f, int64_t site,
                      const double* gP, double* out) {
   if (check_params(P) != ORC_OK) return ORC_EINVAL;

@@ -101,6 +101,17 @@ int orc_conservative_force_one(const orc_params* P, int64_t np, const double* x,
  * density gP [3] at r.  Used for sampled comparisons on large lattices.     */
 int orc_site_collide(const orc_params* P, int64_t step, const double* f,
                      int64_t site, const double* gP, double* out /*[2][19]*/);
+/* Coupling force (friction + solvation + random) on particle p at position
+ * xp with velocity vp (after the step's half kick and drift), from the
+ * post-streaming state f at step n.                                        */
+void orc_coupling_force_one(const orc_params* P, int64_t step, const double* f, const double* xp,
+                            const double* vp, int32_t type, int64_t p, double* Fc /*[3]*/);
+/* Particle force density at one node: -sum_p W_p(site) F_coup,p over the
+ * particles whose 8 nodes include the site (positions/velocities after the
+ * half kick and drift).                                                    */
+void orc_particle_force_at(const orc_params* P, int64_t step, const double* f, int64_t np,
+                           const double* x, const double* v, const int32_t* type, int64_t site,
+                           double* gP /*[3]*/);
 /* u_c and grad rho_zeta at one node (the quantities the particles see).    */
 void orc_node_fields(const orc_params* P, const double* f, int64_t site,
                      double* uc /*[3]*/, double* grad /*[2][3]*/);

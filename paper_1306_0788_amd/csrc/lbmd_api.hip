@@ -1,0 +1,543 @@
+// C-ABI entry points of the lbmd library (declared in include/lbmd.h).
+// Host-side runtime: validation, device allocation, step sequencing on one
+// HIP stream, the device status latch and host transfers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbmd_internal.h"
+
+using namespace lbmd;
+
+namespace {
+
+int fail(lbmd_ctx* h, int code, const char* msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+int hip_fail(lbmd_ctx* h, hipError_t e, const char* where) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+  if (h) h->err = buf;
+  return e == hipErrorOutOfMemory ? LBMD_ENOMEM : LBMD_EDEVICE;
+}
+
+#define HIPCHECK(h, expr)                              \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(h, e_, #expr); \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return hipSuccess;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+bool finite_all(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+int validate(const lbmd_params* p, std::string& why) {
+  if (!p) return why = "params is NULL", LBMD_EINVAL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return why = "lattice size must be >= 1", LBMD_EINVAL;
+  const double n = double(p->nx) * p->ny * p->nz;
+  if (n > 2147483647.0) return why = "lattice has more than 2^31-1 sites", LBMD_EINVAL;
+  // kernels address the 19 arrays of a component through one buffer
+  // resource (32-bit byte range)
+  if (19.0 * n * (p->precision == LBMD_FP64 ? 8.0 : 4.0) >= 4294967296.0)
+    return why = "the 19 population arrays of a component must stay below 4 GiB", LBMD_EINVAL;
+  if (p->precision != LBMD_FP64 && p->precision != LBMD_FP32) return why = "unknown precision", LBMD_EINVAL;
+  if (p->forcing != LBMD_FORCE_PAPER && p->forcing != LBMD_FORCE_SHIFT) return why = "unknown forcing", LBMD_EINVAL;
+  if (p->kernel != LBMD_KERNEL_FUSED && p->kernel != LBMD_KERNEL_TWOPASS) return why = "unknown kernel", LBMD_EINVAL;
+  for (int c = 0; c < 2; ++c)
+    if (!(p->tau[c] > 0.5) || !std::isfinite(p->tau[c])) return why = "tau must be > 1/2", LBMD_EINVAL;
+  if (p->forcing == LBMD_FORCE_PAPER && p->tau[0] != p->tau[1])
+    return why = "the paper's forcing needs the same relaxation for both components", LBMD_EINVAL;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      if (!std::isfinite(p->G[a][b])) return why = "G must be finite", LBMD_EINVAL;
+  if (!std::isfinite(p->gamma) || p->gamma < 0) return why = "gamma must be finite and >= 0", LBMD_EINVAL;
+  if (!std::isfinite(p->kappa[0]) || !std::isfinite(p->kappa[1])) return why = "kappa must be finite", LBMD_EINVAL;
+  if (!(p->mass > 0) || !std::isfinite(p->mass)) return why = "mass must be > 0", LBMD_EINVAL;
+  if (!(p->kT >= 0) || !std::isfinite(p->kT)) return why = "kT must be finite and >= 0", LBMD_EINVAL;
+  if (p->kT > 0 && p->forcing == LBMD_FORCE_SHIFT) return why = "fluctuations need the paper's forcing", LBMD_EINVAL;
+  if (p->check_every < 0 || p->reserved != 0) return why = "bad check_every/reserved", LBMD_EINVAL;
+  return LBMD_OK;
+}
+
+// read and latch the device status (synchronises the stream)
+int poll_status(lbmd_ctx* h) {
+  if (h->latched) return LBMD_EUNSTABLE;
+  uint32_t st = 0;
+  long long bad = 0;
+  HIPCHECK(h, hipMemcpyAsync(&st, h->status, sizeof st, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(&bad, h->bad_step, sizeof bad, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  if (st) {
+    h->latched = true;
+    char buf[200];
+    snprintf(buf, sizeof buf, "numerical failure at step %lld (%s%s)", bad, (st & 1u) ? "fluid density <= 0 or non-finite" : "",
+             (st & 2u) ? ((st & 1u) ? ", non-finite particle state" : "non-finite particle state") : "");
+    h->err = buf;
+    return LBMD_EUNSTABLE;
+  }
+  return LBMD_OK;
+}
+
+void free_particles(lbmd_ctx* h) {
+  dfree(h->x);
+  dfree(h->v);
+  dfree(h->F);
+  dfree(h->Fc);
+  dfree(h->type);
+  dfree(h->cell_of);
+  dfree(h->rank_of);
+  dfree(h->cell_perm);
+  dfree(h->flag_list);
+  dfree(h->red_part);
+  h->np_cap = 0;
+  h->flag_cap = 0;
+  h->red_part_cap = 0;
+}
+
+void free_bonds(lbmd_ctx* h) {
+  dfree(h->bond_start);
+  dfree(h->bond_nbr);
+  h->nbonds = 0;
+}
+
+// (re)build the pair-force cell grid for the current cut-off
+int setup_cells(lbmd_ctx* h) {
+  dfree(h->cell_count);
+  dfree(h->cell_start);
+  dfree(h->scan_block);
+  h->rcut = 0.0;
+  if (h->pair.wca_on) h->rcut = std::max(h->rcut, std::sqrt(h->pair.wca_rc2));
+  if (h->pair.dh_on) h->rcut = std::max(h->rcut, h->pair.dh_rc);
+  const int L[3] = {h->p.nx, h->p.ny, h->p.nz};
+  h->ncells = 1;
+  for (int a = 0; a < 3; ++a) {
+    int n = h->rcut > 0 ? int(std::floor(L[a] / h->rcut)) : 1;
+    h->ncell[a] = n >= 3 ? n : 1;  // fewer than 3 cells would alias neighbours
+    h->ncells *= h->ncell[a];
+  }
+  if (!(h->pair.wca_on || h->pair.dh_on)) return LBMD_OK;
+  HIPCHECK(h, dalloc(&h->cell_count, h->ncells + 1));
+  HIPCHECK(h, dalloc(&h->cell_start, h->ncells + 1));
+  HIPCHECK(h, dalloc(&h->scan_block, (h->ncells + 1 + 1023) / 1024 + 1));
+  HIPCHECK(h, hipMemsetAsync(h->cell_count, 0, (h->ncells + 1) * sizeof(int32_t), h->stream));
+  return LBMD_OK;
+}
+
+int ensure_coupling_buffers(lbmd_ctx* h) {
+  if (h->mask) return LBMD_OK;
+  const size_t words = (h->N + 31) / 32;
+  HIPCHECK(h, dalloc(&h->mask, words));
+  HIPCHECK(h, hipMemsetAsync(h->mask, 0, words * sizeof(uint32_t), h->stream));
+  HIPCHECK(h, hipMalloc(&h->rec, 9 * h->N * h->s_bytes));
+  HIPCHECK(h, hipMalloc(&h->gP, 3 * h->N * h->s_bytes));
+  HIPCHECK(h, hipMemsetAsync(h->gP, 0, 3 * h->N * h->s_bytes, h->stream));
+  HIPCHECK(h, hipMemsetAsync(h->rec, 0, 9 * h->N * h->s_bytes, h->stream));
+  return LBMD_OK;
+}
+
+int ensure_staging(lbmd_ctx* h, size_t n) {
+  if (h->export_cap >= n) return LBMD_OK;
+  dfree(h->export_tmp);
+  h->export_cap = 0;
+  HIPCHECK(h, dalloc(&h->export_tmp, n));
+  h->export_cap = n;
+  return LBMD_OK;
+}
+
+}  // namespace
+
+namespace lbmd {
+hipError_t prof_begin(lbmd_ctx* h) {
+  if (!h->prof_on) return hipSuccess;
+  if (2 * h->prof_n + 2 > h->prof_ev.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      if (hipError_t r = hipEventCreate(&e)) return r;
+      h->prof_ev.push_back(e);
+    }
+  }
+  return hipEventRecord(h->prof_ev[2 * h->prof_n], h->stream);
+}
+hipError_t prof_end(lbmd_ctx* h) {
+  if (!h->prof_on) return hipSuccess;
+  hipError_t r = hipEventRecord(h->prof_ev[2 * h->prof_n + 1], h->stream);
+  h->prof_n += 1;
+  return r;
+}
+}  // namespace lbmd
+
+extern "C" {
+
+int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, lbmd_handle* out) {
+  if (!out) return LBMD_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (int rc = validate(p, why)) {
+    fprintf(stderr, "lbmd_create: %s\n", why.c_str());
+    return rc;
+  }
+  if (rho_init && !finite_all(rho_init, size_t(2) * p->nx * p->ny * p->nz)) return LBMD_EINVAL;
+  lbmd_ctx* h = new (std::nothrow) lbmd_ctx();
+  if (!h) return LBMD_ENOMEM;
+  h->p = *p;
+  h->N = int64_t(p->nx) * p->ny * p->nz;
+  h->s_bytes = p->precision == LBMD_FP64 ? 8 : 4;
+  h->types.ntypes = 1;
+  for (int t = 0; t < LBMD_MAX_TYPES; ++t) {
+    h->types.kappa[t][0] = p->kappa[0];
+    h->types.kappa[t][1] = p->kappa[1];
+    h->types.mass[t] = p->mass;
+    h->types.charge[t] = 0.0;
+  }
+  std::memset(&h->pair, 0, sizeof h->pair);
+  auto bail = [&](int rc) {
+    lbmd_destroy(h);
+    return rc;
+  };
+  if (hipGetDevice(&h->device) != hipSuccess) return bail(LBMD_EDEVICE);
+  if (hip_stream) {
+    h->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) return bail(LBMD_EDEVICE);
+    h->own_stream = true;
+  }
+  const size_t pop = size_t(2) * 19 * h->N * h->s_bytes;
+  for (int b = 0; b < 2; ++b)
+    if (hipMalloc(&h->f[b], pop) != hipSuccess) return bail(LBMD_ENOMEM);
+  if (hipMalloc(&h->rho, 2 * h->N * h->s_bytes) != hipSuccess) return bail(LBMD_ENOMEM);
+  // reduction partials: the largest launch is the two-row fused tiling with
+  // one plane per block, or the two-pass collide grid
+  const int64_t tiles_x = (p->nx + 63) / 64;
+  h->red_fluid_cap = std::max<int64_t>(tiles_x * ((p->ny + 1) / 2) * p->nz, tiles_x * ((p->ny + 3) / 4) * p->nz);
+  if (dalloc(&h->red_fluid, 5 * h->red_fluid_cap) != hipSuccess) return bail(LBMD_ENOMEM);
+  if (dalloc(&h->red_out, 8) != hipSuccess || dalloc(&h->status, 1) != hipSuccess ||
+      dalloc(&h->bad_step, 1) != hipSuccess || dalloc(&h->nflag, 1) != hipSuccess)
+    return bail(LBMD_ENOMEM);
+  const long long never = 0x7fffffffffffffffLL;
+  if (hipMemsetAsync(h->red_out, 0, 8 * sizeof(double), h->stream) != hipSuccess ||
+      hipMemsetAsync(h->status, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
+      hipMemcpyAsync(h->bad_step, &never, sizeof never, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipMemsetAsync(h->nflag, 0, sizeof(int32_t), h->stream) != hipSuccess)
+    return bail(LBMD_EDEVICE);
+  double* rho_dev = nullptr;
+  if (rho_init) {
+    if (dalloc(&rho_dev, 2 * h->N) != hipSuccess) return bail(LBMD_ENOMEM);
+    if (hipMemcpyAsync(rho_dev, rho_init, 2 * h->N * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+      return bail(LBMD_EDEVICE);
+  }
+  if (fluid_init(h, rho_dev) != hipSuccess) return bail(LBMD_EDEVICE);
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LBMD_EDEVICE);
+  dfree(rho_dev);
+  // tiling default: 8 rows per block (a full wave per row); z chunk sized so
+  // the launch holds several blocks per compute unit
+  h->tile_y = p->ny >= 8 ? 8 : (p->ny >= 4 ? 4 : 2);
+  h->tile_z = std::max(1, std::min(p->nz, 16));
+  *out = h;
+  return LBMD_OK;
+}
+
+int lbmd_destroy(lbmd_handle h) {
+  if (!h) return LBMD_EINVAL;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (int b = 0; b < 2; ++b)
+    if (h->f[b]) (void)hipFree(h->f[b]);
+  if (h->rho) (void)hipFree(h->rho);
+  if (h->rec) (void)hipFree(h->rec);
+  if (h->gP) (void)hipFree(h->gP);
+  dfree(h->mask);
+  free_particles(h);
+  free_bonds(h);
+  dfree(h->cell_count);
+  dfree(h->cell_start);
+  dfree(h->scan_block);
+  dfree(h->red_fluid);
+  dfree(h->red_out);
+  dfree(h->status);
+  dfree(h->bad_step);
+  dfree(h->nflag);
+  dfree(h->export_tmp);
+  for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return LBMD_OK;
+}
+
+int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double* vel, const int32_t* type) {
+  if (!h || n < 0 || (n > 0 && !pos)) return fail(h, LBMD_EINVAL, "set_particles: bad arguments");
+  if (n > (int64_t(1) << 28)) return fail(h, LBMD_EINVAL, "set_particles: too many particles");
+  if (!finite_all(pos, 3 * n) || (vel && !finite_all(vel, 3 * n)))
+    return fail(h, LBMD_EINVAL, "set_particles: non-finite input");
+  std::vector<double> x(3 * n), v(3 * n, 0.0);
+  std::vector<int32_t> t(n, 0);
+  const double L[3] = {double(h->p.nx), double(h->p.ny), double(h->p.nz)};
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      double q = pos[3 * i + a];
+      q -= L[a] * std::floor(q / L[a]);
+      if (q >= L[a]) q -= L[a];
+      if (q < 0) q += L[a];
+      x[3 * i + a] = q;
+      if (vel) v[3 * i + a] = vel[3 * i + a];
+    }
+  if (type)
+    for (int64_t i = 0; i < n; ++i) {
+      if (type[i] < 0 || type[i] >= h->types.ntypes) return fail(h, LBMD_EINVAL, "set_particles: bad type");
+      t[i] = type[i];
+    }
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  if (n != h->np) free_bonds(h);
+  if (n > h->np_cap) {
+    free_particles(h);
+    HIPCHECK(h, dalloc(&h->x, 3 * n));
+    HIPCHECK(h, dalloc(&h->v, 3 * n));
+    HIPCHECK(h, dalloc(&h->F, 3 * n));
+    HIPCHECK(h, dalloc(&h->Fc, 3 * n));
+    HIPCHECK(h, dalloc(&h->type, n));
+    HIPCHECK(h, dalloc(&h->cell_of, n));
+    HIPCHECK(h, dalloc(&h->rank_of, n));
+    HIPCHECK(h, dalloc(&h->cell_perm, n));
+    HIPCHECK(h, dalloc(&h->flag_list, 8 * n));
+    HIPCHECK(h, dalloc(&h->red_part, 3 * ((n + 255) / 256)));
+    h->np_cap = n;
+    h->flag_cap = 8 * n;
+    h->red_part_cap = (n + 255) / 256;
+  }
+  h->np = n;
+  h->red_part_used = 0;
+  if (n > 0) {
+    if (int rc = ensure_coupling_buffers(h)) return rc;
+    HIPCHECK(h, hipMemcpyAsync(h->x, x.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(h->v, v.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(h->type, t.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(h, hipMemsetAsync(h->F, 0, 3 * n * sizeof(double), h->stream));
+    HIPCHECK(h, hipMemsetAsync(h->Fc, 0, 3 * n * sizeof(double), h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+  }
+  return LBMD_OK;
+}
+
+int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, const double* mass,
+                            const double* charge) {
+  if (!h || ntypes < 1 || ntypes > LBMD_MAX_TYPES || !kappa || !mass)
+    return fail(h, LBMD_EINVAL, "set_particle_types: bad arguments");
+  for (int t = 0; t < ntypes; ++t)
+    if (!(mass[t] > 0) || !std::isfinite(mass[t]) || !std::isfinite(kappa[2 * t]) || !std::isfinite(kappa[2 * t + 1]) ||
+        (charge && !std::isfinite(charge[t])))
+      return fail(h, LBMD_EINVAL, "set_particle_types: bad values");
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  h->types.ntypes = ntypes;
+  for (int t = 0; t < ntypes; ++t) {
+    h->types.kappa[t][0] = kappa[2 * t];
+    h->types.kappa[t][1] = kappa[2 * t + 1];
+    h->types.mass[t] = mass[t];
+    h->types.charge[t] = charge ? charge[t] : 0.0;
+  }
+  return LBMD_OK;
+}
+
+int lbmd_set_pair_potential(lbmd_handle h, int32_t kind, const double* q) {
+  if (!h) return LBMD_EINVAL;
+  const double half = 0.5 * std::min({h->p.nx, h->p.ny, h->p.nz});
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  switch (kind) {
+    case LBMD_PAIR_WCA:
+      if (!q) {
+        h->pair.wca_on = 0;
+        break;
+      }
+      if (!(q[0] > 0) || !(q[1] >= 0) || !std::isfinite(q[0]) || !std::isfinite(q[1]))
+        return fail(h, LBMD_EINVAL, "WCA: sigma > 0, eps >= 0");
+      if (std::pow(2.0, 1.0 / 6.0) * q[0] >= half) return fail(h, LBMD_EINVAL, "WCA cut-off >= half the box");
+      h->pair.wca_on = 1;
+      h->pair.wca_sigma = q[0];
+      h->pair.wca_eps = q[1];
+      h->pair.wca_rc2 = std::pow(2.0, 1.0 / 3.0) * q[0] * q[0];
+      break;
+    case LBMD_PAIR_DH:
+      if (!q) {
+        h->pair.dh_on = 0;
+        break;
+      }
+      if (!(q[0] >= 0) || !(q[1] > 0) || !std::isfinite(q[0]) || !std::isfinite(q[1]) || !std::isfinite(q[2]))
+        return fail(h, LBMD_EINVAL, "DH: kappa_D >= 0, r_c > 0");
+      if (q[1] >= half) return fail(h, LBMD_EINVAL, "DH cut-off >= half the box");
+      h->pair.dh_on = 1;
+      h->pair.dh_kappa = q[0];
+      h->pair.dh_rc = q[1];
+      h->pair.dh_lB = q[2];
+      break;
+    case LBMD_BOND_FENE:
+      if (!q) {
+        h->pair.fene_on = 0;
+        break;
+      }
+      if (!(q[0] >= 0) || !(q[1] > 0) || !std::isfinite(q[0]) || !std::isfinite(q[1]))
+        return fail(h, LBMD_EINVAL, "FENE: k >= 0, R0 > 0");
+      if (q[1] >= half) return fail(h, LBMD_EINVAL, "FENE R0 >= half the box");
+      h->pair.fene_on = 1;
+      h->pair.fene_k = q[0];
+      h->pair.fene_R0 = q[1];
+      break;
+    default:
+      return fail(h, LBMD_EINVAL, "unknown potential kind");
+  }
+  return setup_cells(h);
+}
+
+int lbmd_set_bonds(lbmd_handle h, int64_t nb, const int32_t* pairs) {
+  if (!h || nb < 0 || (nb > 0 && !pairs)) return fail(h, LBMD_EINVAL, "set_bonds: bad arguments");
+  std::vector<int32_t> deg(h->np + 1, 0);
+  for (int64_t b = 0; b < nb; ++b) {
+    const int32_t i = pairs[2 * b], j = pairs[2 * b + 1];
+    if (i < 0 || j < 0 || i >= h->np || j >= h->np || i == j) return fail(h, LBMD_EINVAL, "set_bonds: bad index");
+    if (++deg[i] > 8 || ++deg[j] > 8) return fail(h, LBMD_EINVAL, "set_bonds: more than 8 bonds on a particle");
+  }
+  std::vector<int32_t> start(h->np + 1, 0), nbr(2 * nb);
+  for (int64_t i = 0; i < h->np; ++i) start[i + 1] = start[i] + deg[i];
+  std::vector<int32_t> fill(start.begin(), start.end() - 1);
+  for (int64_t b = 0; b < nb; ++b) {
+    const int32_t i = pairs[2 * b], j = pairs[2 * b + 1];
+    nbr[fill[i]++] = j;
+    nbr[fill[j]++] = i;
+  }
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  free_bonds(h);
+  if (nb == 0) return LBMD_OK;
+  HIPCHECK(h, dalloc(&h->bond_start, h->np + 1));
+  HIPCHECK(h, dalloc(&h->bond_nbr, 2 * nb));
+  HIPCHECK(h, hipMemcpyAsync(h->bond_start, start.data(), (h->np + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                             h->stream));
+  HIPCHECK(h, hipMemcpyAsync(h->bond_nbr, nbr.data(), 2 * nb * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  h->nbonds = nb;
+  return LBMD_OK;
+}
+
+int lbmd_step(lbmd_handle h, int64_t nsteps) {
+  if (!h || nsteps < 0) return fail(h, LBMD_EINVAL, "step: bad arguments");
+  if (h->latched) return fail(h, LBMD_ESTATE, "step: a numerical failure is latched");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const bool parts = h->np > 0;
+    if (parts) HIPCHECK(h, particles_begin(h));
+    else h->red_part_used = 0;
+    HIPCHECK(h, fluid_pass_a(h));
+    if (parts) HIPCHECK(h, particles_forces(h));
+    HIPCHECK(h, fluid_pass_b(h));
+    if (parts) HIPCHECK(h, particles_end(h));
+    HIPCHECK(h, finalize_step(h));
+    h->cur = 1 - h->cur;
+    h->step += 1;
+    if (h->p.check_every > 0 && h->step % h->p.check_every == 0)
+      if (int rc = poll_status(h)) return rc;
+  }
+  return LBMD_OK;
+}
+
+int lbmd_sync(lbmd_handle h) {
+  if (!h) return LBMD_EINVAL;
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  return poll_status(h);
+}
+
+int lbmd_get_fields(lbmd_handle h, uint32_t mask, double* out, int32_t out_is_device) {
+  if (!h || !out || mask == 0 || (mask & ~(LBMD_RHO | LBMD_U | LBMD_POP)))
+    return fail(h, LBMD_EINVAL, "get_fields: bad arguments");
+  size_t n = 0;
+  if (mask & LBMD_RHO) n += 2 * h->N;
+  if (mask & LBMD_U) n += 3 * h->N;
+  if (mask & LBMD_POP) n += 38 * h->N;
+  double* dst = out;
+  if (!out_is_device) {
+    if (int rc = ensure_staging(h, n)) return rc;
+    dst = h->export_tmp;
+  }
+  HIPCHECK(h, fluid_export(h, mask, dst));
+  if (!out_is_device) {
+    HIPCHECK(h, hipMemcpyAsync(out, dst, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+  }
+  return out_is_device ? LBMD_OK : poll_status(h);
+}
+
+int lbmd_get_particles(lbmd_handle h, double* pos, double* vel, double* force, double* fcoup) {
+  if (!h) return LBMD_EINVAL;
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  const size_t b = 3 * h->np * sizeof(double);
+  if (h->np > 0) {
+    if (pos) HIPCHECK(h, hipMemcpyAsync(pos, h->x, b, hipMemcpyDeviceToHost, h->stream));
+    if (vel) HIPCHECK(h, hipMemcpyAsync(vel, h->v, b, hipMemcpyDeviceToHost, h->stream));
+    if (force) HIPCHECK(h, hipMemcpyAsync(force, h->F, b, hipMemcpyDeviceToHost, h->stream));
+    if (fcoup) HIPCHECK(h, hipMemcpyAsync(fcoup, h->Fc, b, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+  }
+  return poll_status(h);
+}
+
+int lbmd_set_populations(lbmd_handle h, const double* pop) {
+  if (!h || !pop) return fail(h, LBMD_EINVAL, "set_populations: NULL");
+  if (int rc = ensure_staging(h, 38 * h->N)) return rc;
+  HIPCHECK(h, hipMemcpyAsync(h->export_tmp, pop, 38 * h->N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, fluid_import(h, h->export_tmp));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  return LBMD_OK;
+}
+
+int lbmd_reductions(lbmd_handle h, double* out, int64_t* step_out) {
+  if (!h || !out) return LBMD_EINVAL;
+  HIPCHECK(h, hipMemcpyAsync(out, h->red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  if (step_out) *step_out = h->step - 1;
+  return poll_status(h);
+}
+
+int64_t lbmd_get_step(lbmd_handle h) { return h ? h->step : -1; }
+
+const char* lbmd_last_error(lbmd_handle h) { return h ? h->err.c_str() : "NULL handle"; }
+
+int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z) {
+  if (!h || !(tile_y == 2 || tile_y == 4 || tile_y == 8 || tile_y == 16) || tile_z < 1)
+    return fail(h, LBMD_EINVAL, "set_tiling: tile_y in {2,4,8,16}, tile_z >= 1");
+  h->tile_y = tile_y;
+  h->tile_z = tile_z;
+  return LBMD_OK;
+}
+
+int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t* launches) {
+  if (!h) return LBMD_EINVAL;
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  double tot = 0.0;
+  for (size_t k = 0; k < h->prof_n; ++k) {
+    float ms = 0.0f;
+    HIPCHECK(h, hipEventElapsedTime(&ms, h->prof_ev[2 * k], h->prof_ev[2 * k + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = int64_t(h->prof_n);
+  if (enable) h->prof_n = 0;
+  h->prof_on = enable != 0;
+  return LBMD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,684 @@
+// Fluid kernels of the lbmd library (gfx950, wave64).
+//
+// Storage: populations are structure-of-arrays [zeta][i][z][y][x] (x fastest)
+// in "pull" form: the value stored for velocity i at site s is the
+// post-collision population that streams to s + c_i.  A step therefore reads
+// src[zeta][i][s - c_i] (the post-streaming population at s) and writes the
+// new post-collision value to dst[zeta][i][s]: 38 coalesced reads and 38
+// coalesced writes per site, the algorithmic minimum of one LB step.
+//
+// The Shan-Chen force at s needs the densities of the 18 neighbours
+// (Sec. 2, Eq. SCforce), each a sum of 19 pulled populations.  Two kernel
+// organisations are provided:
+//   two-pass  k_density writes rho[2][N]; k_collide reads it back as a
+//             stencil (118 values of traffic per site);
+//   fused     k_fused marches a 64 x TY tile along z, builds the density of
+//             each new plane (tile + one-site ring) into a 4-slot LDS ring,
+//             keeps the tile's own populations of the next plane in
+//             registers, and collides the middle plane: HBM traffic stays at
+//             38 + 38 values per site; the ring's extra loads hit L2.
+// Particle coupling: the collision at a node touched by a particle needs the
+// particle force, which needs the node's u_c and grad rho of the same step.
+// The fused kernel therefore collides every site without it, stores u_c and
+// the neighbour sums at the touched nodes (records), and k_fix re-collides
+// only those nodes once the particle forces are spread.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "lbmd_internal.h"
+#include "lbmd_site.h"
+
+namespace lbmd {
+
+__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+
+// Population arrays are read and written through one buffer resource per
+// component: base address in scalar registers, the population's offset
+// i*N*sizeof(S) as the scalar offset and the site as a 32-bit vector offset.
+// A component's 19 arrays must stay below 4 GiB (checked at create).  An
+// access outside the resource's range reads zero instead of faulting.
+template <class S>
+struct Pops {
+  __amdgpu_buffer_rsrc_t r[2];
+  uint32_t pstride;  // N * sizeof(S)
+};
+template <class S>
+__device__ __forceinline__ Pops<S> make_pops(const S* base, int64_t N) {
+  Pops<S> p;
+  const uint32_t bytes = uint32_t(19 * N * int64_t(sizeof(S)));
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+    p.r[c] = __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(base + int64_t(c) * 19 * N), (short)0, int(bytes),
+                                               0x00020000);
+  p.pstride = uint32_t(N * int64_t(sizeof(S)));
+  return p;
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(vo), int(so), 0));
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(vo), int(so), 0));
+}
+// aux = 2: non-temporal store (the new populations are not read again by
+// this step)
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(vo), int(so), 2);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r,
+                                        int(vo), int(so), 2);
+}
+
+// pulled populations of site (x,y,z): f_i(s) = src[i][s - c_i]
+template <class S, class C>
+__device__ __forceinline__ void pull(const Pops<S>& src, int x, int y, int z, int nx, int ny, int nz,
+                                     C (&f)[2][19]) {
+  const uint32_t xm = wrapi(x - 1, nx), xp = wrapi(x + 1, nx), x0 = x;
+  const uint32_t plane = uint32_t(nx) * uint32_t(ny);
+  const uint32_t ym = wrapi(y - 1, ny) * nx, yp = wrapi(y + 1, ny) * nx, y0 = uint32_t(y) * nx;
+  const uint32_t zm = wrapi(z - 1, nz) * plane, zp = wrapi(z + 1, nz) * plane, z0 = uint32_t(z) * plane;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const uint32_t sx = D3Q19::cx[i] > 0 ? xm : (D3Q19::cx[i] < 0 ? xp : x0);
+    const uint32_t sy = D3Q19::cy[i] > 0 ? ym : (D3Q19::cy[i] < 0 ? yp : y0);
+    const uint32_t sz = D3Q19::cz[i] > 0 ? zm : (D3Q19::cz[i] < 0 ? zp : z0);
+    const uint32_t vo = (sz + sy + sx) * uint32_t(sizeof(S));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) f[c][i] = C(bload(src.r[c], vo, uint32_t(i) * src.pstride, (S*)nullptr));
+  }
+}
+
+template <class S, class C>
+__device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&f)[2][19]) {
+  const uint32_t vo = s * uint32_t(sizeof(S));
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < 19; ++i) bstore(S(f[c][i]), dst.r[c], vo, uint32_t(i) * dst.pstride);
+}
+
+__device__ __forceinline__ void flag_unstable(uint32_t* status, long long* bad, uint32_t bit, long long step) {
+  atomicOr(status, bit);
+  atomicMin(bad, step);
+}
+
+template <class C>
+__device__ __forceinline__ bool moments_ok(const SiteOut<C>& o) {
+  return o.rho[0] > C(0) && o.rho[1] > C(0) && isfinite(o.rho[0]) && isfinite(o.rho[1]) && isfinite(o.j[0]) &&
+         isfinite(o.j[1]) && isfinite(o.j[2]);
+}
+
+// wave64 sum of a double
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block sum of 5 doubles into out[5] (thread 0 writes); nthreads multiple of 64
+template <int NW>
+__device__ __forceinline__ void block_sum5(double (&v)[5], double* out) {
+  __shared__ double part[NW][5];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) v[q] = wave_sum(v[q]);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) part[wv][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double s = 0;
+    for (int w = 0; w < NW; ++w) s += part[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------ init / io
+template <class S>
+__global__ void k_init(S* __restrict__ f, const double* __restrict__ rho, int nx, int ny, int nz) {
+  const int64_t N = int64_t(nx) * ny * nz;
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const int x = int(s % nx), y = int((s / nx) % ny), z = int(s / (int64_t(nx) * ny));
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int64_t t = (int64_t(wrapi(z + D3Q19::cz[i], nz)) * ny + wrapi(y + D3Q19::cy[i], ny)) * nx +
+                      wrapi(x + D3Q19::cx[i], nx);
+    for (int c = 0; c < 2; ++c)
+      f[(int64_t(c) * 19 + i) * N + s] = S(weight<double>(i) * (rho ? rho[c * N + t] : 1.0));
+  }
+}
+
+template <class S>
+__global__ void k_import(S* __restrict__ f, const double* __restrict__ pop, int nx, int ny, int nz) {
+  const int64_t N = int64_t(nx) * ny * nz;
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const int x = int(s % nx), y = int((s / nx) % ny), z = int(s / (int64_t(nx) * ny));
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int64_t t = (int64_t(wrapi(z + D3Q19::cz[i], nz)) * ny + wrapi(y + D3Q19::cy[i], ny)) * nx +
+                      wrapi(x + D3Q19::cx[i], nx);
+    for (int c = 0; c < 2; ++c) f[(int64_t(c) * 19 + i) * N + s] = S(pop[(int64_t(c) * 19 + i) * N + t]);
+  }
+}
+
+// density field rho[2][N] (two-pass kernel and exports)
+template <class S>
+__global__ void k_density(const S* __restrict__ src, S* __restrict__ rho, int nx, int ny, int nz) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const int64_t N = int64_t(nx) * ny * nz;
+  S f[2][19];
+  pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
+  const int64_t s = (int64_t(z) * ny + y) * nx + x;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    S r = f[c][0];
+#pragma unroll
+    for (int i = 1; i < 19; ++i) r += f[c][i];
+    rho[c * N + s] = r;
+  }
+}
+
+// neighbour sums from a density field
+template <class S, class C>
+__device__ __forceinline__ void nsum_field(const S* __restrict__ rho, int x, int y, int z, int nx, int ny, int nz,
+                                          int64_t N, C (&NA)[3], C (&NB)[3]) {
+  C a[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    const int64_t t = (int64_t(wrapi(z + D3Q19::cz[i], nz)) * ny + wrapi(y + D3Q19::cy[i], ny)) * nx +
+                      wrapi(x + D3Q19::cx[i], nx);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const C wr = weight<C>(i) * C(rho[c * N + t]);
+      if (D3Q19::cx[i]) a[c][0] += D3Q19::cx[i] > 0 ? wr : -wr;
+      if (D3Q19::cy[i]) a[c][1] += D3Q19::cy[i] > 0 ? wr : -wr;
+      if (D3Q19::cz[i]) a[c][2] += D3Q19::cz[i] > 0 ? wr : -wr;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    NA[q] = a[0][q];
+    NB[q] = a[1][q];
+  }
+}
+
+template <class C>
+__device__ __forceinline__ void velocity_uc(const SiteOut<C>& o, const C (&NA)[3], const C (&NB)[3],
+                                            const FluidConsts<C>& K, C (&uc)[3]) {
+  const C rt = o.rho[0] + o.rho[1];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const C g0 = -o.rho[0] * (K.G[0][0] * NA[a] + K.G[0][1] * NB[a]);
+    const C g1 = -o.rho[1] * (K.G[1][0] * NA[a] + K.G[1][1] * NB[a]);
+    uc[a] = (o.j[a] + C(0.5) * (g0 + g1)) / rt;
+  }
+}
+
+template <class C>
+__device__ __forceinline__ SiteOut<C> moments_only(const C (&f)[2][19]) {
+  SiteOut<C> o;
+  o.j[0] = o.j[1] = o.j[2] = 0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    C r = f[c][0], jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      r += f[c][i];
+      if (D3Q19::cx[i]) jx += D3Q19::cx[i] > 0 ? f[c][i] : -f[c][i];
+      if (D3Q19::cy[i]) jy += D3Q19::cy[i] > 0 ? f[c][i] : -f[c][i];
+      if (D3Q19::cz[i]) jz += D3Q19::cz[i] > 0 ? f[c][i] : -f[c][i];
+    }
+    o.rho[c] = r;
+    o.j[0] += jx;
+    o.j[1] += jy;
+    o.j[2] += jz;
+  }
+  return o;
+}
+
+// export: rho [2][N], u_c [3][N], populations [2][19][N] as float64
+template <class S>
+__global__ void k_export(const S* __restrict__ src, const S* __restrict__ rho, double* __restrict__ out,
+                         FluidConsts<S> K, uint32_t mask) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int z = blockIdx.z;
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
+  if (x >= nx || y >= ny) return;
+  const int64_t N = K.N;
+  const int64_t s = (int64_t(z) * ny + y) * nx + x;
+  S f[2][19];
+  pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
+  double* o = out;
+  if (mask & LBMD_RHO) {
+    o[s] = double(rho[s]);
+    o[N + s] = double(rho[N + s]);
+    o += 2 * N;
+  }
+  if (mask & LBMD_U) {
+    S NA[3], NB[3], uc[3];
+    nsum_field<S, S>(rho, x, y, z, nx, ny, nz, N, NA, NB);
+    SiteOut<S> m = moments_only<S>(f);
+    velocity_uc<S>(m, NA, NB, K, uc);
+    for (int a = 0; a < 3; ++a) o[a * N + s] = double(uc[a]);
+    o += 3 * N;
+  }
+  if (mask & LBMD_POP)
+    for (int c = 0; c < 2; ++c)
+      for (int i = 0; i < 19; ++i) o[(int64_t(c) * 19 + i) * N + s] = double(f[c][i]);
+}
+
+// ------------------------------------------------------------ two-pass path
+template <class S, int FORCING, bool NOISE>
+__global__ __launch_bounds__(256) void k_collide(const S* __restrict__ src, S* __restrict__ dst,
+                                                 const S* __restrict__ rho, FluidConsts<S> K,
+                                                 const uint32_t* __restrict__ mask, const S* __restrict__ gP,
+                                                 double* __restrict__ red, uint32_t* status, long long* bad) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int z = blockIdx.z;
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
+  const int64_t N = K.N;
+  double acc[5] = {0, 0, 0, 0, 0};
+  if (x < nx && y < ny) {
+    const int64_t s = (int64_t(z) * ny + y) * nx + x;
+    S f[2][19], NA[3], NB[3], gp[3] = {0, 0, 0};
+    pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
+    nsum_field<S, S>(rho, x, y, z, nx, ny, nz, N, NA, NB);
+    if (mask && (mask[s >> 5] >> (s & 31)) & 1u)
+      for (int a = 0; a < 3; ++a) gp[a] = gP[a * N + s];
+    SiteOut<S> o = collide<S, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s));
+    store<S, S>(make_pops<S>(dst, N), uint32_t(s), f);
+    if (!moments_ok(o)) flag_unstable(status, bad, 1u, K.step);
+    acc[0] = o.rho[0];
+    acc[1] = o.rho[1];
+    acc[2] = o.j[0];
+    acc[3] = o.j[1];
+    acc[4] = o.j[2];
+  }
+  const int64_t blk = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  block_sum5<4>(acc, red + 5 * blk);
+}
+
+// records (u_c and neighbour sums) at the touched nodes, from the density field
+template <class S>
+__global__ void k_records(const S* __restrict__ src, const S* __restrict__ rho, FluidConsts<S> K,
+                          const int32_t* __restrict__ list, const int32_t* __restrict__ nlist, S* __restrict__ rec) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= *nlist) return;
+  const int64_t N = K.N;
+  const int64_t s = list[t];
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
+  const int x = int(s % nx), y = int((s / nx) % ny), z = int(s / (int64_t(nx) * ny));
+  S f[2][19], NA[3], NB[3], uc[3];
+  pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
+  nsum_field<S, S>(rho, x, y, z, nx, ny, nz, N, NA, NB);
+  SiteOut<S> o = moments_only<S>(f);
+  velocity_uc<S>(o, NA, NB, K, uc);
+  for (int a = 0; a < 3; ++a) {
+    rec[a * N + s] = NA[a];
+    rec[(3 + a) * N + s] = NB[a];
+    rec[(6 + a) * N + s] = uc[a];
+  }
+}
+
+// clear the per-node particle force and the touched-node mask
+template <class S>
+__global__ void k_clear_nodes(const int32_t* __restrict__ list, const int32_t* __restrict__ nlist, S* __restrict__ gP,
+                              uint32_t* __restrict__ mask, int64_t N) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= *nlist) return;
+  const int64_t s = list[t];
+  for (int a = 0; a < 3; ++a) gP[a * N + s] = S(0);
+  mask[s >> 5] = 0u;
+}
+
+// ------------------------------------------------------------ fused path
+// Block = TY waves; wave w owns row y0+w, lane l owns column x0+l of a 64-wide
+// tile.  The block marches z over [z0, z1).  LDS ring: 4 density planes of
+// the tile plus a one-site border (the border sites are loaded by lanes of
+// every wave, a few per wave).
+template <class S, int TY, int FORCING, bool NOISE>
+__global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S* __restrict__ dst_, FluidConsts<S> K,
+                                                    int tz, int tiles_x, int tiles_y, const uint32_t* __restrict__ mask,
+                                                    S* __restrict__ rec, double* __restrict__ red, uint32_t* status,
+                                                    long long* bad) {
+  using C = S;
+  constexpr int RW = 66, RH = TY + 2;
+  __shared__ C ring[4][2][RH][RW];
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
+  const int64_t N = K.N;
+  const int64_t plane = int64_t(nx) * ny;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const Pops<S> src = make_pops(src_, N), dst = make_pops<S>(dst_, N);
+
+  // tile of this block; consecutive block ids walk z-chunks of one column
+  // first so that the 8 XCDs each get contiguous z ranges
+  const int nchunk = (nz + tz - 1) / tz;
+  const int bid = blockIdx.x;
+  const int bz = bid % nchunk;
+  const int bxy = bid / nchunk;
+  const int bx = bxy % tiles_x, by = bxy / tiles_x;
+  const int x0 = bx * 64, y0 = by * TY, z0 = bz * tz, z1 = min(z0 + tz, nz);
+  const int twv = min(64, nx - x0), thv = min(TY, ny - y0);
+  const bool inside = lane < twv && wv < thv;
+  const int x = x0 + lane, y = y0 + wv;
+  const int ringA = twv + 2;
+  const int nring = 2 * ringA + 2 * thv;
+
+  C cur[2][19], nxt[2][19];
+  double acc[5] = {0, 0, 0, 0, 0};
+
+  // density of the tile's own sites of plane zp -> ring; populations -> nxt
+  auto load_interior = [&](int zp_raw, int slot) {
+    const int zz = wrapi(zp_raw, nz);
+    if (inside) {
+      pull<S, C>(src, x, y, zz, nx, ny, nz, nxt);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        C r = nxt[c][0];
+#pragma unroll
+        for (int i = 1; i < 19; ++i) r += nxt[c][i];
+        ring[slot][c][wv + 1][lane + 1] = r;
+      }
+    }
+  };
+  // density of the one-site border of plane zp -> ring (a few lanes per wave)
+  auto load_border = [&](int zp_raw, int slot) {
+    const int zz = wrapi(zp_raw, nz);
+    for (int h = lane * TY + wv; h < nring; h += 64 * TY) {
+      int hr, hc;
+      if (h < ringA) {
+        hr = 0;
+        hc = h;
+      } else if (h < 2 * ringA) {
+        hr = thv + 1;
+        hc = h - ringA;
+      } else if (h < 2 * ringA + thv) {
+        hr = 1 + (h - 2 * ringA);
+        hc = 0;
+      } else {
+        hr = 1 + (h - 2 * ringA - thv);
+        hc = twv + 1;
+      }
+      C hf[2][19];
+      pull<S, C>(src, wrapi(x0 - 1 + hc, nx), wrapi(y0 - 1 + hr, ny), zz, nx, ny, nz, hf);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        C r = hf[c][0];
+#pragma unroll
+        for (int i = 1; i < 19; ++i) r += hf[c][i];
+        ring[slot][c][hr][hc] = r;
+      }
+    }
+  };
+
+  // prologue: planes z0-1 and z0 complete, border of z0+1; cur = plane z0
+  load_interior(z0 - 1, 0);
+  load_border(z0 - 1, 0);
+  load_interior(z0, 1);
+  load_border(z0, 1);
+  load_border(z0 + 1, 2);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < 19; ++i) cur[c][i] = nxt[c][i];
+
+  // iteration z: interior of z+1, barrier, collide z, border of z+2.  Ring
+  // slots: plane q lives in slot (q - z0 + 1) & 3; the border of z+2 goes to
+  // the slot last read in iteration z-1, which this iteration's barrier
+  // separates from it.
+  for (int z = z0; z < z1; ++z) {
+    const int k = z - z0;
+    load_interior(z + 1, (k + 2) & 3);
+    __syncthreads();
+    if (inside) {
+      const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
+      C NA[3] = {0, 0, 0}, NB[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 1; i < 19; ++i) {
+        const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
+        const int sl = cz > 0 ? sp : (cz < 0 ? sm : s0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const C wr = weight<C>(i) * ring[sl][c][wv + 1 + cy][lane + 1 + cx];
+          C(&Nc)[3] = c == 0 ? NA : NB;
+          if (cx) Nc[0] += cx > 0 ? wr : -wr;
+          if (cy) Nc[1] += cy > 0 ? wr : -wr;
+          if (cz) Nc[2] += cz > 0 ? wr : -wr;
+        }
+      }
+      const int64_t s = z * plane + int64_t(y) * nx + x;
+      const C gp[3] = {0, 0, 0};
+      const bool touched = mask && ((mask[s >> 5] >> (s & 31)) & 1u);
+      SiteOut<C> o = collide<C, FORCING, NOISE>(cur, NA, NB, gp, K, uint32_t(s));
+      store<S, C>(dst, uint32_t(s), cur);
+      if (touched) {
+        C uc[3];
+        velocity_uc<C>(o, NA, NB, K, uc);
+        for (int a = 0; a < 3; ++a) {
+          rec[a * N + s] = NA[a];
+          rec[(3 + a) * N + s] = NB[a];
+          rec[(6 + a) * N + s] = uc[a];
+        }
+      }
+      if (!moments_ok(o)) flag_unstable(status, bad, 1u, K.step);
+      acc[0] += o.rho[0];
+      acc[1] += o.rho[1];
+      acc[2] += o.j[0];
+      acc[3] += o.j[1];
+      acc[4] += o.j[2];
+    }
+    if (z + 2 <= z1) load_border(z + 2, (k + 3) & 3);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < 19; ++i) cur[c][i] = nxt[c][i];
+  }
+  block_sum5<TY>(acc, red + 5 * int64_t(bid));
+}
+
+// re-collide the touched nodes with the spread particle force; clears the
+// node force and the mask as it goes
+template <class S, int FORCING, bool NOISE>
+__global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __restrict__ dst, FluidConsts<S> K,
+                                             const int32_t* __restrict__ list, const int32_t* __restrict__ nlist,
+                                             const S* __restrict__ rec, S* __restrict__ gP, uint32_t* __restrict__ mask) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= *nlist) return;
+  const int64_t N = K.N;
+  const int64_t s = list[t];
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
+  const int x = int(s % nx), y = int((s / nx) % ny), z = int(s / (int64_t(nx) * ny));
+  S f[2][19], NA[3], NB[3], gp[3];
+  pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
+  for (int a = 0; a < 3; ++a) {
+    NA[a] = rec[a * N + s];
+    NB[a] = rec[(3 + a) * N + s];
+    gp[a] = gP[a * N + s];
+    gP[a * N + s] = S(0);
+  }
+  mask[s >> 5] = 0u;
+  collide<S, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s));
+  store<S, S>(make_pops<S>(dst, N), uint32_t(s), f);
+}
+
+// final reductions: fluid partials [nf][5], particle partials [np][3] -> out[8]
+__global__ void k_finalize(const double* __restrict__ rf, int64_t nf, const double* __restrict__ rp, int64_t npb,
+                           double* __restrict__ out, int32_t* nflag) {
+  __shared__ double sh[256];
+  for (int q = 0; q < 8; ++q) {
+    double s = 0;
+    if (q < 5)
+      for (int64_t b = threadIdx.x; b < nf; b += 256) s += rf[5 * b + q];
+    else
+      for (int64_t b = threadIdx.x; b < npb; b += 256) s += rp[3 * b + (q - 5)];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = sh[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *nflag = 0;
+}
+
+// ------------------------------------------------------------ launchers
+template <class S>
+FluidConsts<S> consts(const lbmd_ctx* h) {
+  FluidConsts<S> K;
+  K.nx = h->p.nx;
+  K.ny = h->p.ny;
+  K.nz = h->p.nz;
+  K.N = h->N;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) K.G[a][b] = S(h->p.G[a][b]);
+  for (int c = 0; c < 2; ++c) {
+    K.tau[c] = S(h->p.tau[c]);
+    K.omega[c] = S(1.0 / h->p.tau[c]);
+  }
+  K.kT = S(h->p.kT);
+  K.forcing = h->p.forcing;
+  K.noise = h->p.kT > 0.0;
+  K.seed = h->p.seed;
+  K.step = h->step;
+  return K;
+}
+
+static dim3 plane_grid(const lbmd_ctx* h) {
+  return dim3((h->p.nx + 63) / 64, (h->p.ny + 3) / 4, h->p.nz);
+}
+
+template <class S>
+static hipError_t init_t(lbmd_ctx* h, const double* rho_dev) {
+  const int64_t N = h->N;
+  hipLaunchKernelGGL(k_init<S>, dim3((N + 255) / 256), dim3(256), 0, h->stream, (S*)h->f[h->cur], rho_dev, h->p.nx,
+                     h->p.ny, h->p.nz);
+  return hipGetLastError();
+}
+hipError_t fluid_init(lbmd_ctx* h, const double* rho_dev) {
+  return h->p.precision == LBMD_FP64 ? init_t<double>(h, rho_dev) : init_t<float>(h, rho_dev);
+}
+
+template <class S>
+static hipError_t import_t(lbmd_ctx* h, const double* pop) {
+  const int64_t N = h->N;
+  hipLaunchKernelGGL(k_import<S>, dim3((N + 255) / 256), dim3(256), 0, h->stream, (S*)h->f[h->cur], pop, h->p.nx,
+                     h->p.ny, h->p.nz);
+  return hipGetLastError();
+}
+hipError_t fluid_import(lbmd_ctx* h, const double* pop) {
+  return h->p.precision == LBMD_FP64 ? import_t<double>(h, pop) : import_t<float>(h, pop);
+}
+
+template <class S>
+static hipError_t export_t(lbmd_ctx* h, uint32_t mask, double* out) {
+  const S* src = (const S*)h->f[h->cur];
+  hipLaunchKernelGGL(k_density<S>, plane_grid(h), dim3(256), 0, h->stream, src, (S*)h->rho, h->p.nx, h->p.ny,
+                     h->p.nz);
+  hipLaunchKernelGGL(k_export<S>, plane_grid(h), dim3(256), 0, h->stream, src, (const S*)h->rho, out, consts<S>(h),
+                     mask);
+  return hipGetLastError();
+}
+hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out) {
+  return h->p.precision == LBMD_FP64 ? export_t<double>(h, mask, out) : export_t<float>(h, mask, out);
+}
+
+template <class S, int FORCING, bool NOISE>
+static void launch_fused(lbmd_ctx* h, const S* src, S* dst, const FluidConsts<S>& K) {
+  const int tiles_x = (h->p.nx + 63) / 64;
+  const int ty = h->tile_y;
+  const int tiles_y = (h->p.ny + ty - 1) / ty;
+  const int tz = std::max(1, std::min(h->tile_z, h->p.nz));
+  const int nchunk = (h->p.nz + tz - 1) / tz;
+  const int64_t nblk = int64_t(tiles_x) * tiles_y * nchunk;
+  h->red_fluid_used = nblk;
+  const uint32_t* mask = h->np > 0 ? h->mask : nullptr;
+#define LBMD_FUSED(TY)                                                                                       \
+  hipLaunchKernelGGL((k_fused<S, TY, FORCING, NOISE>), dim3(nblk), dim3(64 * TY), 0, h->stream, src, dst, K, tz, \
+                     tiles_x, tiles_y, mask, (S*)h->rec, h->red_fluid, h->status, h->bad_step)
+  switch (ty) {
+    case 2: LBMD_FUSED(2); break;
+    case 4: LBMD_FUSED(4); break;
+    case 16: LBMD_FUSED(16); break;
+    default: LBMD_FUSED(8); break;
+  }
+#undef LBMD_FUSED
+}
+
+template <class S, int FORCING, bool NOISE>
+static hipError_t pass_a_t(lbmd_ctx* h) {
+  const S* src = (const S*)h->f[h->cur];
+  S* dst = (S*)h->f[1 - h->cur];
+  FluidConsts<S> K = consts<S>(h);
+  if (h->p.kernel == LBMD_KERNEL_FUSED) {
+    if (hipError_t e = prof_begin(h)) return e;
+    launch_fused<S, FORCING, NOISE>(h, src, dst, K);
+    if (hipError_t e = prof_end(h)) return e;
+  } else {
+    hipLaunchKernelGGL(k_density<S>, plane_grid(h), dim3(256), 0, h->stream, src, (S*)h->rho, h->p.nx, h->p.ny,
+                       h->p.nz);
+    if (h->np > 0)
+      hipLaunchKernelGGL(k_records<S>, dim3((h->flag_cap + 255) / 256), dim3(256), 0, h->stream, src,
+                         (const S*)h->rho, K, h->flag_list, h->nflag, (S*)h->rec);
+  }
+  return hipGetLastError();
+}
+
+template <class S, int FORCING, bool NOISE>
+static hipError_t pass_b_t(lbmd_ctx* h) {
+  const S* src = (const S*)h->f[h->cur];
+  S* dst = (S*)h->f[1 - h->cur];
+  FluidConsts<S> K = consts<S>(h);
+  if (h->p.kernel == LBMD_KERNEL_FUSED) {
+    if (h->np > 0)
+      hipLaunchKernelGGL((k_fix<S, FORCING, NOISE>), dim3((h->flag_cap + 255) / 256), dim3(256), 0, h->stream, src,
+                         dst, K, h->flag_list, h->nflag, (const S*)h->rec, (S*)h->gP, h->mask);
+  } else {
+    dim3 g = plane_grid(h);
+    h->red_fluid_used = int64_t(g.x) * g.y * g.z;
+    if (hipError_t e = prof_begin(h)) return e;
+    hipLaunchKernelGGL((k_collide<S, FORCING, NOISE>), g, dim3(256), 0, h->stream, src, dst, (const S*)h->rho, K,
+                       h->np > 0 ? h->mask : nullptr, (const S*)h->gP, h->red_fluid, h->status, h->bad_step);
+    if (hipError_t e = prof_end(h)) return e;
+    if (h->np > 0)
+      hipLaunchKernelGGL(k_clear_nodes<S>, dim3((h->flag_cap + 255) / 256), dim3(256), 0, h->stream, h->flag_list,
+                         h->nflag, (S*)h->gP, h->mask, h->N);
+  }
+  return hipGetLastError();
+}
+
+template <template <class, int, bool> class F>
+struct Dispatch {};
+
+#define LBMD_DISPATCH(NAME)                                                                    \
+  hipError_t fluid_##NAME(lbmd_ctx* h) {                                                       \
+    const bool noise = h->p.kT > 0.0;                                                          \
+    if (h->p.precision == LBMD_FP64) {                                                         \
+      if (h->p.forcing == LBMD_FORCE_SHIFT) return NAME##_t<double, LBMD_FORCE_SHIFT, false>(h); \
+      return noise ? NAME##_t<double, LBMD_FORCE_PAPER, true>(h)                               \
+                   : NAME##_t<double, LBMD_FORCE_PAPER, false>(h);                             \
+    }                                                                                          \
+    if (h->p.forcing == LBMD_FORCE_SHIFT) return NAME##_t<float, LBMD_FORCE_SHIFT, false>(h);  \
+    return noise ? NAME##_t<float, LBMD_FORCE_PAPER, true>(h) : NAME##_t<float, LBMD_FORCE_PAPER, false>(h); \
+  }
+LBMD_DISPATCH(pass_a)
+LBMD_DISPATCH(pass_b)
+#undef LBMD_DISPATCH
+
+hipError_t finalize_step(lbmd_ctx* h) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->red_fluid, h->red_fluid_used, h->red_part,
+                     h->red_part_used, h->red_out, h->nflag);
+  return hipGetLastError();
+}
+
+}  // namespace lbmd

@@ -1,0 +1,191 @@
+// Internal declarations of the lbmd HIP library (gfx950).  Device helpers,
+// the context structure and the kernel launchers shared by the translation
+// units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmd.h"
+
+namespace lbmd {
+
+// ---------------------------------------------------------------- D3Q19
+// Velocities (Appendix, Eq. velo) with opposite pairs adjacent; weights
+// (Eq. weights).  The order is the exported population order.
+struct D3Q19 {
+  static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+};
+template <class C>
+__host__ __device__ constexpr C weight(int i) {
+  return i == 0 ? C(1) / C(3) : (i <= 6 ? C(1) / C(18) : C(1) / C(36));
+}
+
+// ------------------------------------------------------------ Philox4x32-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds; each round
+// multiplies words 0 and 2 by fixed 32-bit constants, xors the high halves
+// with the other two words and the round key, and bumps the key by two Weyl
+// constants.  Counter layout used by the library: (index, step low word,
+// draw block | stream tag << 16, step high word); key = seed.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c.x;
+    const uint64_t p1 = uint64_t(0xCD9E8D57u) * c.z;
+    U4 n;
+    n.x = uint32_t(p1 >> 32) ^ c.y ^ k0;
+    n.y = uint32_t(p1);
+    n.z = uint32_t(p0 >> 32) ^ c.w ^ k1;
+    n.w = uint32_t(p0);
+    c = n;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Box-Muller pair from two words; u = (word + 1/2) / 2^32 in (0, 1).
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1) {
+  const double u1 = (double(a) + 0.5) * 2.3283064365386963e-10;
+  const double u2 = (double(b) + 0.5) * 2.3283064365386963e-10;
+  const double r = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
+  const float u1 = (float(a) + 0.5f) * 2.3283064365386963e-10f;
+  const float u2 = (float(b) + 0.5f) * 2.3283064365386963e-10f;
+  const float r = __fsqrt_rn(-2.0f * __logf(u1));
+  // hardware sine/cosine take the angle in turns
+  z0 = r * __builtin_amdgcn_cosf(u2);
+  z1 = r * __builtin_amdgcn_sinf(u2);
+}
+
+template <class C>
+__device__ __forceinline__ void normals4(uint64_t seed, int64_t step, uint32_t index, uint32_t block,
+                                         uint32_t tag, C* z) {
+  U4 c{index, uint32_t(step), block | (tag << 16), uint32_t(uint64_t(step) >> 32)};
+  U4 o = philox4x32_10(c, uint32_t(seed), uint32_t(seed >> 32));
+  box_muller(o.x, o.y, z[0], z[1]);
+  box_muller(o.z, o.w, z[2], z[3]);
+}
+
+// --------------------------------------------------------------- context
+struct ParticleTypes {
+  double kappa[LBMD_MAX_TYPES][2];
+  double mass[LBMD_MAX_TYPES];
+  double charge[LBMD_MAX_TYPES];
+  int32_t ntypes;
+};
+
+struct PairParams {
+  int32_t wca_on, dh_on, fene_on;
+  double wca_sigma, wca_eps, wca_rc2;
+  double dh_kappa, dh_rc, dh_lB;
+  double fene_k, fene_R0;
+};
+
+// Scalar parameters of one fluid step, passed by value to the kernels.
+template <class C>
+struct FluidConsts {
+  int nx, ny, nz;
+  int64_t N;
+  C G[2][2];
+  C omega[2];   // 1/tau
+  C tau[2];
+  C kT;
+  int forcing;  // LBMD_FORCE_*
+  int noise;    // kT > 0
+  uint64_t seed;
+  int64_t step;
+};
+
+}  // namespace lbmd
+
+struct lbmd_ctx {
+  lbmd_params p;
+  int64_t N = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t s_bytes = 8;  // bytes per stored population
+
+  // fluid state: populations in the pull layout (buffer value at s for
+  // velocity i streams to s + c_i at the next step)
+  void* f[2] = {nullptr, nullptr};
+  int cur = 0;
+  void* rho = nullptr;  // [2][N] density field (two-pass kernel)
+  int tile_y = 8, tile_z = 16;
+
+  // particle coupling
+  uint32_t* mask = nullptr;  // one bit per site: touched by a particle
+  int32_t* flag_list = nullptr;
+  int32_t* nflag = nullptr;  // device counter
+  int64_t flag_cap = 0;
+  void* rec = nullptr;  // [9][N]: N_A(3), N_B(3), u_c(3) at touched nodes
+  void* gP = nullptr;   // [3][N]: particle force density accumulated at nodes
+
+  // particles (always float64)
+  int64_t np = 0, np_cap = 0;
+  double *x = nullptr, *v = nullptr, *F = nullptr, *Fc = nullptr;
+  int32_t* type = nullptr;
+  int32_t* cell_of = nullptr;  // pair-force cell of each particle
+  int32_t* rank_of = nullptr;  // arrival rank inside its cell
+  lbmd::ParticleTypes types;
+  lbmd::PairParams pair;
+  double rcut = 0.0;  // largest non-bonded cut-off
+  int ncell[3] = {1, 1, 1};
+  int64_t ncells = 0;
+  int32_t *cell_count = nullptr, *cell_start = nullptr, *cell_perm = nullptr;
+  int32_t* scan_block = nullptr;
+  int64_t nbonds = 0;
+  int32_t *bond_start = nullptr, *bond_nbr = nullptr;  // CSR, both directions
+
+  // reductions and status
+  double* red_fluid = nullptr;  // [blocks][5]
+  int64_t red_fluid_cap = 0;
+  int64_t red_fluid_used = 0;
+  double* red_part = nullptr;  // [blocks][3]
+  int64_t red_part_cap = 0;
+  int64_t red_part_used = 0;
+  double* red_out = nullptr;     // [8]
+  uint32_t* status = nullptr;    // bit 0: fluid, bit 1: particles
+  long long* bad_step = nullptr; // first failing step
+  double* export_tmp = nullptr;  // staging for host transfers
+  size_t export_cap = 0;
+
+  int64_t step = 0;
+  bool latched = false;
+  std::string err;
+
+  // optional event timing of the collide-stream kernel
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;  // start/stop pairs
+  size_t prof_n = 0;                // pairs recorded
+};
+
+namespace lbmd {
+// event pair around a timed launch (no-op unless timing is enabled)
+hipError_t prof_begin(lbmd_ctx* h);
+hipError_t prof_end(lbmd_ctx* h);
+// launchers (lbmd_fluid.hip)
+hipError_t fluid_init(lbmd_ctx* h, const double* rho_dev);
+hipError_t fluid_import(lbmd_ctx* h, const double* pop_dev);
+hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out_dev);
+hipError_t fluid_pass_a(lbmd_ctx* h);  // moments, SC force, records (+ fused collide)
+hipError_t fluid_pass_b(lbmd_ctx* h);  // collision with the particle force
+hipError_t finalize_step(lbmd_ctx* h);  // reductions, counters
+// launchers (lbmd_particles.hip)
+hipError_t particles_begin(lbmd_ctx* h);  // reduction terms, half kick, drift, flags, cells
+hipError_t particles_forces(lbmd_ctx* h); // coupling + conservative forces, spread
+hipError_t particles_end(lbmd_ctx* h);    // second half kick
+}  // namespace lbmd

@@ -1,0 +1,370 @@
+// Particle kernels of the lbmd library: velocity-Verlet integration of the
+// Langevin equation of Sec. 2 (Eq. NEWTON) coupled to the lattice fluid.
+//
+// Per step (time step 1):
+//   k_begin   conservation terms of the state at the start of the step,
+//             half kick, drift, periodic wrap; marks the 8 nodes around each
+//             particle in a bit mask and appends newly marked nodes to a
+//             compact list (one atomic per wave); counts particles per cell
+//             of the pair-force cell list
+//   k_scan_*  exclusive scan of the cell counts, then a scatter into
+//             cell-sorted order
+//   k_forces  trilinear interpolation of u_c and grad rho_zeta from the node
+//             records, friction + solvation (Eq. solvation_kappa) + random
+//             force, conservative pair forces from the cell list and FENE
+//             bonds; the opposite coupling force is spread onto the 8 nodes
+//             with hardware float atomics
+//   k_end     second half kick
+// All particle quantities are float64.
+#include <hip/hip_runtime.h>
+
+#include "lbmd_internal.h"
+
+namespace lbmd {
+
+struct PartArgs {
+  int64_t np;
+  int nx, ny, nz;
+  int64_t N;
+  double gamma, kT;
+  uint64_t seed;
+  int64_t step;
+  ParticleTypes T;
+  PairParams pp;
+  int ncell[3];
+  int use_cells;
+};
+
+__device__ __forceinline__ double wrapd(double x, double L) {
+  x -= L * floor(x / L);
+  if (x >= L) x -= L;
+  if (x < 0.0) x += L;
+  return x;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) { return d - L * floor(d / L + 0.5); }
+
+__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+__device__ __forceinline__ void interp(const double* x, int nx, int ny, int nz, int64_t (&node)[8], double (&W)[8]) {
+  const double fx = floor(x[0]), fy = floor(x[1]), fz = floor(x[2]);
+  const double dx = x[0] - fx, dy = x[1] - fy, dz = x[2] - fz;
+  const int ix = int(fx), iy = int(fy), iz = int(fz);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
+    W[k] = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
+    const int X = wrapi(ix + ox, nx), Y = wrapi(iy + oy, ny), Z = wrapi(iz + oz, nz);
+    node[k] = (int64_t(Z) * ny + Y) * nx + X;
+  }
+}
+
+__device__ __forceinline__ int cell_index(const double* x, const PartArgs& A) {
+  const double L[3] = {double(A.nx), double(A.ny), double(A.nz)};
+  int c[3];
+  for (int a = 0; a < 3; ++a) {
+    int q = int(x[a] / L[a] * A.ncell[a]);
+    c[a] = q < 0 ? 0 : (q >= A.ncell[a] ? A.ncell[a] - 1 : q);
+  }
+  return (c[2] * A.ncell[1] + c[1]) * A.ncell[0] + c[0];
+}
+
+__device__ __forceinline__ void flag_unstable(uint32_t* status, long long* bad, uint32_t bit, long long step) {
+  atomicOr(status, bit);
+  atomicMin(bad, step);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_begin(PartArgs A, double* __restrict__ x, double* __restrict__ v,
+                                               const double* __restrict__ F, const double* __restrict__ Fc,
+                                               const int32_t* __restrict__ type, uint32_t* __restrict__ mask,
+                                               int32_t* __restrict__ list, int32_t* __restrict__ nlist,
+                                               int32_t* __restrict__ cell_count, int32_t* __restrict__ cell_of,
+                                               int32_t* __restrict__ rank_of, double* __restrict__ red) {
+  __shared__ double part[4][3];
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool valid = p < A.np;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double mom[3] = {0, 0, 0};
+  int64_t node[8];
+  double W[8];
+  if (valid) {
+    const int t = type[p];
+    const double m = A.T.mass[t];
+    const double L[3] = {double(A.nx), double(A.ny), double(A.nz)};
+    double xp[3];
+    for (int a = 0; a < 3; ++a) {
+      const double va = v[3 * p + a];
+      mom[a] = m * va + 0.5 * Fc[3 * p + a];
+      const double vn = va + 0.5 * F[3 * p + a] / m;
+      v[3 * p + a] = vn;
+      xp[a] = wrapd(x[3 * p + a] + vn, L[a]);
+      x[3 * p + a] = xp[a];
+    }
+    interp(xp, A.nx, A.ny, A.nz, node, W);
+    if (A.use_cells) {
+      const int c = cell_index(xp, A);
+      cell_of[p] = c;
+      rank_of[p] = atomicAdd(&cell_count[c], 1);
+    }
+  }
+  // mark the 8 nodes; append the ones this thread marked first
+  for (int k = 0; k < 8; ++k) {
+    bool fresh = false;
+    if (valid) {
+      const uint32_t bit = 1u << (node[k] & 31);
+      const uint32_t old = atomicOr(&mask[node[k] >> 5], bit);
+      fresh = !(old & bit);
+    }
+    const unsigned long long b = __ballot(fresh);
+    if (b) {
+      const int leader = __ffsll((long long)b) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(nlist, __popcll(b));
+      base = __shfl(base, leader, 64);
+      if (fresh) list[base + __popcll(b & ((1ull << lane) - 1ull))] = int32_t(node[k]);
+    }
+  }
+  for (int a = 0; a < 3; ++a) mom[a] = wave_sum(mom[a]);
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) part[wv][a] = mom[a];
+  __syncthreads();
+  if (threadIdx.x < 3) red[3 * blockIdx.x + threadIdx.x] = part[0][threadIdx.x] + part[1][threadIdx.x] +
+                                                             part[2][threadIdx.x] + part[3][threadIdx.x];
+}
+
+// exclusive scan of cell counts: per-1024 block, then block totals, then add
+__global__ __launch_bounds__(1024) void k_scan_blocks(const int32_t* __restrict__ cnt, int32_t* __restrict__ start,
+                                                      int32_t* __restrict__ btot, int64_t n) {
+  __shared__ int32_t s[1024];
+  const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  const int32_t v = i < n ? cnt[i] : 0;
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < n) start[i] = s[threadIdx.x] - v;
+  if (threadIdx.x == 1023) btot[blockIdx.x] = s[1023];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ btot, int64_t nb) {
+  __shared__ int32_t s[1024];
+  int32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t v = i < nb ? btot[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) btot[i] = carry + s[threadIdx.x] - v;
+    const int32_t tot = s[1023];
+    __syncthreads();
+    carry += tot;
+  }
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ start, int32_t* __restrict__ cnt, const int32_t* __restrict__ btot,
+                           int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    start[i] += btot[i / 1024];
+    cnt[i] = 0;
+  }
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank_of,
+                          const int32_t* __restrict__ start, int32_t* __restrict__ perm, int64_t np) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < np) perm[start[cell_of[p]] + rank_of[p]] = int32_t(p);
+}
+
+__device__ __forceinline__ void add_radial(double fr, const double (&d)[3], double r, double (&Fp)[3]) {
+  // fr = -dU/dr (positive = repulsive); d points from p to the partner
+  for (int a = 0; a < 3; ++a) Fp[a] -= fr * d[a] / r;
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_forces(PartArgs A, const double* __restrict__ x, const double* __restrict__ v,
+                                                double* __restrict__ F, double* __restrict__ Fc,
+                                                const int32_t* __restrict__ type, const C* __restrict__ rec,
+                                                C* __restrict__ gP, const int32_t* __restrict__ cell_start,
+                                                const int32_t* __restrict__ cell_count_unused,
+                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ cell_of,
+                                                const int32_t* __restrict__ bstart, const int32_t* __restrict__ bnbr,
+                                                uint32_t* status, long long* bad) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= A.np) return;
+  const int64_t N = A.N;
+  const int t = type[p];
+  const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
+  int64_t node[8];
+  double W[8];
+  interp(xp, A.nx, A.ny, A.nz, node, W);
+  // interpolated fluid velocity and lattice density gradients (grad = N/c_s^2)
+  double up[3] = {0, 0, 0}, gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int64_t s = node[k];
+    for (int a = 0; a < 3; ++a) {
+      gA[a] += W[k] * 3.0 * double(rec[a * N + s]);
+      gB[a] += W[k] * 3.0 * double(rec[(3 + a) * N + s]);
+      up[a] += W[k] * double(rec[(6 + a) * N + s]);
+    }
+  }
+  double R[4] = {0, 0, 0, 0};
+  if (A.kT > 0.0) {
+    normals4<double>(A.seed, A.step, uint32_t(p), 0u, 1u, R);
+    const double amp = sqrt(2.0 * A.kT * A.gamma);
+    for (int a = 0; a < 3; ++a) R[a] *= amp;
+  }
+  double fc[3];
+  for (int a = 0; a < 3; ++a)
+    fc[a] = -A.gamma * (v[3 * p + a] - up[a]) - (A.T.kappa[t][0] * gA[a] + A.T.kappa[t][1] * gB[a]) + R[a];
+  // conservative forces
+  double Fp[3] = {0, 0, 0};
+  const double L[3] = {double(A.nx), double(A.ny), double(A.nz)};
+  if (A.use_cells) {
+    const int c = cell_of[p];
+    const int cx = c % A.ncell[0], cy = (c / A.ncell[0]) % A.ncell[1], cz = c / (A.ncell[0] * A.ncell[1]);
+    const int lo[3] = {A.ncell[0] >= 3 ? -1 : 0, A.ncell[1] >= 3 ? -1 : 0, A.ncell[2] >= 3 ? -1 : 0};
+    const int hi[3] = {A.ncell[0] >= 3 ? 1 : 0, A.ncell[1] >= 3 ? 1 : 0, A.ncell[2] >= 3 ? 1 : 0};
+    const double qp = A.T.charge[t];
+    for (int dz = lo[2]; dz <= hi[2]; ++dz)
+      for (int dy = lo[1]; dy <= hi[1]; ++dy)
+        for (int dx = lo[0]; dx <= hi[0]; ++dx) {
+          const int nc = (wrapi(cz + dz, A.ncell[2]) * A.ncell[1] + wrapi(cy + dy, A.ncell[1])) * A.ncell[0] +
+                         wrapi(cx + dx, A.ncell[0]);
+          const int b = cell_start[nc], e = cell_start[nc + 1];
+          for (int jj = b; jj < e; ++jj) {
+            const int q = perm[jj];
+            if (q == p) continue;
+            double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const double r = sqrt(r2);
+            if (A.pp.wca_on && r2 < A.pp.wca_rc2) {
+              const double s2 = A.pp.wca_sigma * A.pp.wca_sigma / r2;
+              const double s6 = s2 * s2 * s2;
+              add_radial(24.0 * A.pp.wca_eps * (2.0 * s6 * s6 - s6) / r, d, r, Fp);
+            }
+            if (A.pp.dh_on && r < A.pp.dh_rc) {
+              const double qq = qp * A.T.charge[type[q]];
+              add_radial(qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) / r2, d, r, Fp);
+            }
+          }
+        }
+  }
+  if (A.pp.fene_on && bstart) {
+    for (int jj = bstart[p]; jj < bstart[p + 1]; ++jj) {
+      const int q = bnbr[jj];
+      double d[3];
+      for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double qr = r / A.pp.fene_R0;
+      const double fr = qr < 1.0 ? -A.pp.fene_k * r / (1.0 - qr * qr) : __builtin_nan("");
+      add_radial(fr, d, r, Fp);
+    }
+  }
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) {
+    Fc[3 * p + a] = fc[a];
+    const double Ft = fc[a] + Fp[a];
+    F[3 * p + a] = Ft;
+    ok = ok && isfinite(Ft);
+  }
+  if (!ok) flag_unstable(status, bad, 2u, A.step);
+  // momentum returned to the fluid by the same interpolation
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    for (int a = 0; a < 3; ++a) atomicAdd(&gP[a * N + node[k]], C(-W[k] * fc[a]));
+}
+
+__global__ void k_end(PartArgs A, const double* __restrict__ x, double* __restrict__ v, const double* __restrict__ F,
+                      const int32_t* __restrict__ type, uint32_t* status, long long* bad) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= A.np) return;
+  const double m = A.T.mass[type[p]];
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) {
+    const double vn = v[3 * p + a] + 0.5 * F[3 * p + a] / m;
+    v[3 * p + a] = vn;
+    ok = ok && isfinite(vn) && isfinite(x[3 * p + a]);
+  }
+  if (!ok) flag_unstable(status, bad, 2u, A.step);
+}
+
+// ------------------------------------------------------------ launchers
+static PartArgs args(const lbmd_ctx* h) {
+  PartArgs A;
+  A.np = h->np;
+  A.nx = h->p.nx;
+  A.ny = h->p.ny;
+  A.nz = h->p.nz;
+  A.N = h->N;
+  A.gamma = h->p.gamma;
+  A.kT = h->p.kT;
+  A.seed = h->p.seed;
+  A.step = h->step;
+  A.T = h->types;
+  A.pp = h->pair;
+  for (int a = 0; a < 3; ++a) A.ncell[a] = h->ncell[a];
+  A.use_cells = (h->pair.wca_on || h->pair.dh_on) ? 1 : 0;
+  return A;
+}
+
+hipError_t particles_begin(lbmd_ctx* h) {
+  PartArgs A = args(h);
+  const int64_t nb = (h->np + 255) / 256;
+  h->red_part_used = nb;
+  hipLaunchKernelGGL(k_begin, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, h->type, h->mask,
+                     h->flag_list, h->nflag, h->cell_count, h->cell_of, h->rank_of, h->red_part);
+  if (A.use_cells) {
+    const int64_t n = h->ncells;
+    const int64_t nblk = (n + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nblk), dim3(1024), 0, h->stream, h->cell_count, h->cell_start,
+                       h->scan_block, n + 1);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, h->stream, h->scan_block, (n + 1 + 1023) / 1024);
+    hipLaunchKernelGGL(k_scan_add, dim3((n + 1 + 255) / 256), dim3(256), 0, h->stream, h->cell_start, h->cell_count,
+                       h->scan_block, n + 1);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, h->stream, h->cell_of, h->rank_of, h->cell_start,
+                       h->cell_perm, h->np);
+  }
+  return hipGetLastError();
+}
+
+hipError_t particles_forces(lbmd_ctx* h) {
+  PartArgs A = args(h);
+  const int64_t nb = (h->np + 255) / 256;
+  if (h->p.precision == LBMD_FP64)
+    hipLaunchKernelGGL(k_forces<double>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, h->type,
+                       (const double*)h->rec, (double*)h->gP, h->cell_start, h->cell_count, h->cell_perm, h->cell_of,
+                       h->bond_start, h->bond_nbr, h->status, h->bad_step);
+  else
+    hipLaunchKernelGGL(k_forces<float>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, h->type,
+                       (const float*)h->rec, (float*)h->gP, h->cell_start, h->cell_count, h->cell_perm, h->cell_of,
+                       h->bond_start, h->bond_nbr, h->status, h->bad_step);
+  return hipGetLastError();
+}
+
+hipError_t particles_end(lbmd_ctx* h) {
+  PartArgs A = args(h);
+  hipLaunchKernelGGL(k_end, dim3((h->np + 255) / 256), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->type,
+                     h->status, h->bad_step);
+  return hipGetLastError();
+}
+
+}  // namespace lbmd

@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element on identical seeded inputs.
+
+Tolerances: FP64 storage 1e-12 relative per population after one step
+(rounding order only); FP32 storage 1e-5 after one step and 1e-4 on the
+densities after 100 steps below or just above the spinodal; particles at
+the same levels.  Several sizes are ragged on purpose (not multiples of the
+64 x TY tiles or of the z chunk)."""
+import numpy as np
+import pytest
+
+from paper_1306_0788_amd import lbmd
+from parity_cases import Case, compare, rel_err
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = lbmd.FP64, lbmd.FP32
+PAPER, SHIFT = lbmd.FORCE_PAPER, lbmd.FORCE_SHIFT
+FUSED, TWOPASS = lbmd.KERNEL_FUSED, lbmd.KERNEL_TWOPASS
+
+
+def run_pair(case, steps):
+    print("case shape=%s prec=%d forcing=%d kernel=%d steps=%d" % (case.shape, case.precision, case.forcing,
+                                                                   case.kernel, steps), flush=True)
+    g = case.gpu_sim()
+    o = case.oracle_sim()
+    g.step(steps)
+    assert o.step(steps) == 0
+    assert g.sync() == lbmd.OK, g.last_error()
+    return g, o
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-12), (FP32, 1e-5)])
+@pytest.mark.parametrize("forcing", [PAPER, SHIFT])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_one_step_32cubed(precision, tol, forcing, kernel):
+    """The 32^3 mixture with 64 particles (G_AB = 1.6, gamma = 0.5)."""
+    c = Case((32, 32, 32), precision, forcing, kernel, G=1.6, gamma=0.5, vel_amp=0.02,
+             kappa=((0.3, -0.2),), mass=(2.0,))
+    g, o = run_pair(c, 1)
+    compare(c, g, o, tol, tol, "1 step")
+
+
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_hundred_steps_fp64_paper(kernel):
+    """The 32^3 workload, 100 steps, paper forcing (G rho = 1.6 is above the
+    spinodal: round-off grows by about 40x per 100 steps)."""
+    c = Case((32, 32, 32), FP64, PAPER, kernel, G=1.6, gamma=0.5, mass=(1.0,))
+    g, o = run_pair(c, 100)
+    compare(c, g, o, 1e-10, 1e-10, "100 steps")
+
+
+def test_velocity_shift_error_growth_fp64():
+    """Velocity shift at G = 1.6 is deep in the spinodal (growth ~1e10 per 100
+    steps), so round-off is compared at 20 steps with a looser bound."""
+    c = Case((32, 32, 32), FP64, SHIFT, FUSED, G=1.6, gamma=0.5, mass=(1.0,))
+    g, o = run_pair(c, 20)
+    compare(c, g, o, 1e-9, 1e-9, "20 steps shift")
+
+
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_hundred_steps_fp32_density(kernel):
+    """FP32 storage, 100 steps: densities within 1e-4 of the FP64 oracle."""
+    c = Case((32, 32, 32), FP32, PAPER, kernel, G=1.6, gamma=0.5, mass=(1.0,))
+    g, o = run_pair(c, 100)
+    e = rel_err(g.rho(), o.rho())
+    assert e <= 1e-4, e
+
+
+@pytest.mark.parametrize("shape", [(37, 29, 23), (3, 3, 3), (4, 5, 6), (70, 3, 5), (65, 9, 17), (1, 7, 9)])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_ragged_shapes(shape, kernel):
+    n = 6 if np.prod(shape) < 200 else 40
+    c = Case(shape, FP64, PAPER, kernel, G=1.3, gamma=0.7, npart=n, vel_amp=0.02, kappa=((0.2, 0.1),),
+             mass=(3.0,), amp=0.03)
+    g, o = run_pair(c, 5)
+    compare(c, g, o, 1e-11, 1e-11, "ragged")
+
+
+@pytest.mark.parametrize("tiling", [(2, 1), (4, 3), (8, 5), (16, 40)])
+def test_tilings_agree(tiling):
+    c = Case((37, 29, 23), FP64, PAPER, FUSED, G=1.3, gamma=0.7, npart=40, vel_amp=0.02, tiling=tiling)
+    g, o = run_pair(c, 3)
+    compare(c, g, o, 1e-11, 1e-11, "tiling %s" % (tiling,))
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-12), (FP32, 1e-5)])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_fluctuating_identical_draws(precision, tol, kernel):
+    """kT > 0: both sides draw the same Philox4x32-10 normals for the fluid modes
+    and the particle random force."""
+    c = Case((20, 18, 16), precision, PAPER, kernel, G=1.2, gamma=1.0, kT=1e-4, seed=11, npart=30,
+             kappa=((0.1, 0.0),), mass=(5.0,))
+    g, o = run_pair(c, 3)
+    compare(c, g, o, tol * 10, tol * 10, "noise")
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-11), (FP32, 1e-5)])
+def test_chains_fene_wca_debye_hueckel(precision, tol):
+    """Bead-spring chains (FENE + WCA + screened Debye-Hueckel, all beads
+    charged), solvation on A, fluctuating fluid: the polyelectrolyte set-up at
+    a small box."""
+    c = Case((24, 24, 24), precision, PAPER, FUSED, G=1.8, gamma=1.0, kT=1e-4, seed=3, chains=(6, 20),
+             kappa=((0.1, 0.0),), mass=(2000.0,), charge=(1.0,), wca=(1.0, 1.0), fene=(30.0, 1.5),
+             dh=(1.0, 3.0, 1.0))
+    g, o = run_pair(c, 4)
+    compare(c, g, o, tol, tol, "chains")
+
+
+def test_particles_on_nodes_edges_and_shared_cells():
+    L = 12
+    pos = [[3.0, 4.0, 5.0], [0.0, 0.0, 0.0], [L - 1e-13, 2.5, 7.25], [6.5, 6.5, 6.5], [6.6, 6.4, 6.55],
+           [6.45, 6.52, 6.51], [11.999999, 11.999999, 0.0]]
+    c = Case((L, L, L), FP64, PAPER, FUSED, G=1.2, gamma=0.9, positions=pos, vel_amp=0.05,
+             kappa=((0.4, -0.3),), mass=(50.0,))
+    g, o = run_pair(c, 6)
+    compare(c, g, o, 1e-11, 1e-11, "edges")
+
+
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_no_particles(kernel):
+    c = Case((33, 17, 12), FP32, PAPER, kernel, G=1.5, npart=0)
+    g, o = run_pair(c, 4)
+    compare(c, g, o, 1e-5, 1e-5, "no particles")
+
+
+def test_invariants_on_gpu():
+    """Per-component mass to round-off and the fluid + particle momentum
+    invariant, read from the device reductions."""
+    c = Case((24, 20, 16), FP64, PAPER, FUSED, G=1.4, gamma=0.8, npart=50, vel_amp=0.05,
+             kappa=((0.3, -0.1),), mass=(400.0,), wca=(1.0, 0.05), min_dist=1.3)
+    g = c.gpu_sim()
+    first = None
+    for k in range(60):
+        g.step(1)
+        red, st = g.reductions()
+        assert st == k
+        if first is None:
+            first = red.copy()
+        assert abs(red[0] - first[0]) < 1e-12 * first[0]
+        assert abs(red[1] - first[1]) < 1e-12 * first[1]
+        inv, inv0 = red[2:5] + red[5:8], first[2:5] + first[5:8]
+        assert np.abs(inv - inv0).max() < 1e-12, (k, inv - inv0)
+
+
+def test_determinism_without_particles():
+    c = Case((40, 24, 20), FP32, PAPER, FUSED, G=1.7, npart=0)
+    a = c.gpu_sim()
+    b = c.gpu_sim()
+    a.step(10)
+    b.step(10)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_unstable_state_is_latched():
+    c = Case((16, 16, 16), FP64, PAPER, FUSED, G=1.2, npart=4)
+    g = c.gpu_sim()
+    pop = g.populations()
+    pop[1, :, 100] = -0.01  # rho_B < 0 at one site
+    g.set_populations(pop)
+    g.step(3)
+    assert g.sync() == lbmd.EUNSTABLE
+    assert "step 0" in g.last_error()
+    assert g.step_rc(1) == lbmd.ESTATE
+
+
+def test_invalid_parameters_rejected():
+    with pytest.raises(lbmd.LbmdError):
+        lbmd.Sim((8, 8, 8), tau=(0.5, 0.5))
+    with pytest.raises(lbmd.LbmdError):
+        lbmd.Sim((8, 8, 8), tau=(1.0, 0.9))  # paper forcing needs equal tau
+    with pytest.raises(lbmd.LbmdError):
+        lbmd.Sim((8, 8, 8), forcing=SHIFT, kT=1e-3)
+    s = lbmd.Sim((8, 8, 8))
+    with pytest.raises(lbmd.LbmdError):
+        s.set_pair_potential(lbmd.PAIR_DH, (1.0, 5.0, 1.0))  # cut-off above half the box
+    with pytest.raises(lbmd.LbmdError):
+        s.set_particles([[1.0, np.nan, 2.0]])
