@@ -77,9 +77,14 @@ typedef struct lbmd_ctx* lbmd_handle;
 
 /* fluid kernel organisation (same results up to rounding order) */
 #define LBMD_KERNEL_FUSED 0   /* one pass: density halo in LDS + collide +
-                                 stream, then a sparse fix-up at the nodes the
-                                 particles touch                              */
-#define LBMD_KERNEL_TWOPASS 1 /* density pass, then collide + stream          */
+                                 stream, then a sparse re-collision of the
+                                 nodes the particles touch (best with few
+                                 particles)                                   */
+#define LBMD_KERNEL_TWOPASS 1 /* a density pass (density field, records at the
+                                 touched nodes), then collide + stream with the
+                                 particle force applied in-line               */
+#define LBMD_KERNEL_AUTO 2    /* fused with fewer than one touched node per 128
+                                 sites, two-pass otherwise                    */
 
 /* lbmd_get_fields masks; outputs are concatenated in this order */
 #define LBMD_RHO 1u /* [2][N] */
@@ -99,7 +104,7 @@ typedef struct {
   int32_t nx, ny, nz;  /* periodic lattice, each >= 1                       */
   int32_t precision;   /* LBMD_FP64 or LBMD_FP32                            */
   int32_t forcing;     /* LBMD_FORCE_PAPER or LBMD_FORCE_SHIFT              */
-  int32_t kernel;      /* LBMD_KERNEL_FUSED or LBMD_KERNEL_TWOPASS          */
+  int32_t kernel;      /* LBMD_KERNEL_FUSED, _TWOPASS or _AUTO              */
   double tau[2];       /* BGK relaxation time per component, > 1/2          */
   double G[2][2];      /* coupling g_{zeta zeta'} of the Shan-Chen force
                           (Sec. 2, Eq. SCforce) with psi = rho; G[0][1] ==
@@ -194,10 +199,19 @@ int64_t lbmd_get_step(lbmd_handle h);
 /* Message of the last error on the handle (static storage of the handle). */
 const char* lbmd_last_error(lbmd_handle h);
 
-/* Launch configuration of the fused fluid kernel: z planes marched per block
-   (tile_z >= 1) and rows per block (tile_y in {2, 4, 8, 16}).  Same results;
-   only speed changes.  Errors: LBMD_EINVAL. */
-int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z);
+/* Launch configuration of the z-march fluid kernels: rows per block (tile_y
+   in {2, 4, 8, 16}), z planes marched per block (tile_z >= 1), and flags:
+   LBMD_TILE_HOLD keeps the next plane's populations in registers in the
+   fused kernel (else they are read again from cache), LBMD_TILE_XCD orders
+   the blocks so that tiles sharing border rows run on the same XCD,
+   LBMD_TILE_NT marks the population stores non-temporal.  Same results;
+   only speed changes.  Without this call the library uses 4 rows x 16
+   planes (HOLD | NT) for the fused organisation and 16 rows x 64 planes
+   (XCD | NT) for the two-pass one.  Errors: LBMD_EINVAL. */
+#define LBMD_TILE_HOLD 1
+#define LBMD_TILE_XCD 2
+#define LBMD_TILE_NT 4
+int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z, int32_t flags);
 
 /* Timing of the collide-stream kernel (the fused kernel, or the collide
    kernel of the two-pass organisation): enable = 1 clears the record and

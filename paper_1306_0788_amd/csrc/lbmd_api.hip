@@ -64,7 +64,8 @@ int validate(const lbmd_params* p, std::string& why) {
     return why = "the 19 population arrays of a component must stay below 4 GiB", LBMD_EINVAL;
   if (p->precision != LBMD_FP64 && p->precision != LBMD_FP32) return why = "unknown precision", LBMD_EINVAL;
   if (p->forcing != LBMD_FORCE_PAPER && p->forcing != LBMD_FORCE_SHIFT) return why = "unknown forcing", LBMD_EINVAL;
-  if (p->kernel != LBMD_KERNEL_FUSED && p->kernel != LBMD_KERNEL_TWOPASS) return why = "unknown kernel", LBMD_EINVAL;
+  if (p->kernel != LBMD_KERNEL_FUSED && p->kernel != LBMD_KERNEL_TWOPASS && p->kernel != LBMD_KERNEL_AUTO)
+    return why = "unknown kernel", LBMD_EINVAL;
   for (int c = 0; c < 2; ++c)
     if (!(p->tau[c] > 0.5) || !std::isfinite(p->tau[c])) return why = "tau must be > 1/2", LBMD_EINVAL;
   if (p->forcing == LBMD_FORCE_PAPER && p->tau[0] != p->tau[1])
@@ -131,9 +132,14 @@ int setup_cells(lbmd_ctx* h) {
   if (h->pair.wca_on) h->rcut = std::max(h->rcut, std::sqrt(h->pair.wca_rc2));
   if (h->pair.dh_on) h->rcut = std::max(h->rcut, h->pair.dh_rc);
   const int L[3] = {h->p.nx, h->p.ny, h->p.nz};
+  // cell edge >= the cut-off, and no smaller than the mean particle spacing
+  // (about one particle per cell keeps the 27-cell scan and the scan of the
+  // counts short)
+  double edge = h->rcut;
+  if (h->np > 0) edge = std::max(edge, std::cbrt(double(h->N) / double(h->np)));
   h->ncells = 1;
   for (int a = 0; a < 3; ++a) {
-    int n = h->rcut > 0 ? int(std::floor(L[a] / h->rcut)) : 1;
+    int n = edge > 0 ? int(std::floor(L[a] / edge)) : 1;
     h->ncell[a] = n >= 3 ? n : 1;  // fewer than 3 cells would alias neighbours
     h->ncells *= h->ncell[a];
   }
@@ -150,10 +156,10 @@ int ensure_coupling_buffers(lbmd_ctx* h) {
   const size_t words = (h->N + 31) / 32;
   HIPCHECK(h, dalloc(&h->mask, words));
   HIPCHECK(h, hipMemsetAsync(h->mask, 0, words * sizeof(uint32_t), h->stream));
-  HIPCHECK(h, hipMalloc(&h->rec, 9 * h->N * h->s_bytes));
-  HIPCHECK(h, hipMalloc(&h->gP, 3 * h->N * h->s_bytes));
-  HIPCHECK(h, hipMemsetAsync(h->gP, 0, 3 * h->N * h->s_bytes, h->stream));
-  HIPCHECK(h, hipMemsetAsync(h->rec, 0, 9 * h->N * h->s_bytes, h->stream));
+  HIPCHECK(h, hipMalloc(&h->rec, 16 * h->N * h->s_bytes));
+  HIPCHECK(h, hipMalloc(&h->gP, 4 * h->N * h->s_bytes));
+  HIPCHECK(h, hipMemsetAsync(h->gP, 0, 4 * h->N * h->s_bytes, h->stream));
+  HIPCHECK(h, hipMemsetAsync(h->rec, 0, 16 * h->N * h->s_bytes, h->stream));
   return LBMD_OK;
 }
 
@@ -250,8 +256,6 @@ int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, 
   if (fluid_init(h, rho_dev) != hipSuccess) return bail(LBMD_EDEVICE);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LBMD_EDEVICE);
   dfree(rho_dev);
-  // tiling default: 8 rows per block (a full wave per row); z chunk sized so
-  // the launch holds several blocks per compute unit
   h->tile_y = p->ny >= 8 ? 8 : (p->ny >= 4 ? 4 : 2);
   h->tile_z = std::max(1, std::min(p->nz, 16));
   *out = h;
@@ -324,8 +328,11 @@ int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double
     h->flag_cap = 8 * n;
     h->red_part_cap = (n + 255) / 256;
   }
+  const bool regrid = n != h->np;
   h->np = n;
   h->red_part_used = 0;
+  if (regrid && (h->pair.wca_on || h->pair.dh_on))
+    if (int rc = setup_cells(h)) return rc;
   if (n > 0) {
     if (int rc = ensure_coupling_buffers(h)) return rc;
     HIPCHECK(h, hipMemcpyAsync(h->x, x.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -516,11 +523,15 @@ int64_t lbmd_get_step(lbmd_handle h) { return h ? h->step : -1; }
 
 const char* lbmd_last_error(lbmd_handle h) { return h ? h->err.c_str() : "NULL handle"; }
 
-int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z) {
-  if (!h || !(tile_y == 2 || tile_y == 4 || tile_y == 8 || tile_y == 16) || tile_z < 1)
-    return fail(h, LBMD_EINVAL, "set_tiling: tile_y in {2,4,8,16}, tile_z >= 1");
+int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z, int32_t flags) {
+  if (!h || !(tile_y == 2 || tile_y == 4 || tile_y == 8 || tile_y == 16) || tile_z < 1 || (flags & ~7))
+    return fail(h, LBMD_EINVAL, "set_tiling: tile_y in {2,4,8,16}, tile_z >= 1, flags in 0..7");
   h->tile_y = tile_y;
   h->tile_z = tile_z;
+  h->hold = flags & LBMD_TILE_HOLD ? 1 : 0;
+  h->xcd = flags & LBMD_TILE_XCD ? 1 : 0;
+  h->nt = flags & LBMD_TILE_NT ? 1 : 0;
+  h->tiling_set = true;
   return LBMD_OK;
 }
 

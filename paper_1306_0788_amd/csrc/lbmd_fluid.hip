@@ -61,14 +61,16 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, ui
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, double*) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(vo), int(so), 0));
 }
-// aux = 2: non-temporal store (the new populations are not read again by
-// this step)
+// AUX = 2: non-temporal store hint (the new populations are not read again
+// by this step); AUX = 0: plain store
+template <int AUX>
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(vo), int(so), 2);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(vo), int(so), AUX);
 }
+template <int AUX>
 __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r,
-                                        int(vo), int(so), 2);
+                                        int(vo), int(so), AUX);
 }
 
 // pulled populations of site (x,y,z): f_i(s) = src[i][s - c_i]
@@ -91,12 +93,19 @@ __device__ __forceinline__ void pull(const Pops<S>& src, int x, int y, int z, in
 }
 
 template <class S, class C>
-__device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&f)[2][19]) {
+__device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&f)[2][19], bool nt = true) {
   const uint32_t vo = s * uint32_t(sizeof(S));
+  if (nt) {
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int i = 0; i < 19; ++i) bstore(S(f[c][i]), dst.r[c], vo, uint32_t(i) * dst.pstride);
+      for (int i = 0; i < 19; ++i) bstore<2>(S(f[c][i]), dst.r[c], vo, uint32_t(i) * dst.pstride);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < 19; ++i) bstore<0>(S(f[c][i]), dst.r[c], vo, uint32_t(i) * dst.pstride);
+  }
 }
 
 __device__ __forceinline__ void flag_unstable(uint32_t* status, long long* bad, uint32_t bit, long long step) {
@@ -275,111 +284,145 @@ __global__ void k_export(const S* __restrict__ src, const S* __restrict__ rho, d
       for (int i = 0; i < 19; ++i) o[(int64_t(c) * 19 + i) * N + s] = double(f[c][i]);
 }
 
-// ------------------------------------------------------------ two-pass path
-template <class S, int FORCING, bool NOISE>
-__global__ __launch_bounds__(256) void k_collide(const S* __restrict__ src, S* __restrict__ dst,
-                                                 const S* __restrict__ rho, FluidConsts<S> K,
-                                                 const uint32_t* __restrict__ mask, const S* __restrict__ gP,
-                                                 double* __restrict__ red, uint32_t* status, long long* bad) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int z = blockIdx.z;
-  const int nx = K.nx, ny = K.ny, nz = K.nz;
-  const int64_t N = K.N;
-  double acc[5] = {0, 0, 0, 0, 0};
-  if (x < nx && y < ny) {
-    const int64_t s = (int64_t(z) * ny + y) * nx + x;
-    S f[2][19], NA[3], NB[3], gp[3] = {0, 0, 0};
-    pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
-    nsum_field<S, S>(rho, x, y, z, nx, ny, nz, N, NA, NB);
-    if (mask && (mask[s >> 5] >> (s & 31)) & 1u)
-      for (int a = 0; a < 3; ++a) gp[a] = gP[a * N + s];
-    SiteOut<S> o = collide<S, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s));
-    store<S, S>(make_pops<S>(dst, N), uint32_t(s), f);
-    if (!moments_ok(o)) flag_unstable(status, bad, 1u, K.step);
-    acc[0] = o.rho[0];
-    acc[1] = o.rho[1];
-    acc[2] = o.j[0];
-    acc[3] = o.j[1];
-    acc[4] = o.j[2];
-  }
-  const int64_t blk = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  block_sum5<4>(acc, red + 5 * blk);
+// ------------------------------------------------------------ layouts
+// Per-node records (one 64-byte line per node in FP32, two in FP64), written
+// at the nodes the particles touch: N_A (3), N_B (3), u_c (3).  The
+// particle force density accumulated at a node: gP[4 * s + a].
+constexpr int REC = 16;
+constexpr int GPS = 4;
+
+__global__ void k_zero_words(uint32_t* __restrict__ w, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = 0u;
 }
 
-// records (u_c and neighbour sums) at the touched nodes, from the density field
-template <class S>
-__global__ void k_records(const S* __restrict__ src, const S* __restrict__ rho, FluidConsts<S> K,
-                          const int32_t* __restrict__ list, const int32_t* __restrict__ nlist, S* __restrict__ rec) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= *nlist) return;
-  const int64_t N = K.N;
-  const int64_t s = list[t];
-  const int nx = K.nx, ny = K.ny, nz = K.nz;
-  const int x = int(s % nx), y = int((s / nx) % ny), z = int(s / (int64_t(nx) * ny));
-  S f[2][19], NA[3], NB[3], uc[3];
-  pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
-  nsum_field<S, S>(rho, x, y, z, nx, ny, nz, N, NA, NB);
-  SiteOut<S> o = moments_only<S>(f);
-  velocity_uc<S>(o, NA, NB, K, uc);
-  for (int a = 0; a < 3; ++a) {
-    rec[a * N + s] = NA[a];
-    rec[(3 + a) * N + s] = NB[a];
-    rec[(6 + a) * N + s] = uc[a];
+// ------------------------------------------------------------ z-march tiles
+// Block = TY waves; wave w owns row y0+w, lane l owns column x0+l of a
+// 64-wide tile; the block marches z over [z0, z1).  An LDS ring holds four
+// density planes of the tile plus a one-site border; the border sites are
+// shared out over the lanes of every wave.
+template <int TY>
+struct Tile {
+  int x0, y0, z0, z1, twv, thv, ringA, nring, x, y, lane, wv;
+  bool inside;
+  int bid;
+  __device__ Tile(int nx, int ny, int nz, int tz, int tiles_x, int xcd) {
+    lane = threadIdx.x & 63;
+    wv = threadIdx.x >> 6;
+    const int nchunk = (nz + tz - 1) / tz;
+    const int nblk = gridDim.x;
+    int bx, by, bz;
+    if (xcd) {
+      // blocks are dealt to the 8 XCDs in turn; renumber so that each XCD
+      // runs a contiguous range of tiles ordered x, then y, then z: tiles
+      // that share border rows then run together on one L2
+      const int k = blockIdx.x & 7, m = blockIdx.x >> 3;
+      const int q = nblk >> 3, r = nblk & 7;
+      bid = k * q + min(k, r) + m;
+      const int tiles_y = (ny + TY - 1) / TY;
+      bx = bid % tiles_x;
+      by = (bid / tiles_x) % tiles_y;
+      bz = bid / (tiles_x * tiles_y);
+    } else {
+      // consecutive block ids walk the z chunks of one column of tiles
+      bid = blockIdx.x;
+      bz = bid % nchunk;
+      const int bxy = bid / nchunk;
+      bx = bxy % tiles_x;
+      by = bxy / tiles_x;
+    }
+    x0 = bx * 64;
+    y0 = by * TY;
+    z0 = bz * tz;
+    z1 = min(z0 + tz, nz);
+    twv = min(64, nx - x0);
+    thv = min(TY, ny - y0);
+    inside = lane < twv && wv < thv;
+    x = x0 + lane;
+    y = y0 + wv;
+    ringA = twv + 2;
+    nring = 2 * ringA + 2 * thv;
   }
-}
+  // ring coordinates of border item h: the row below the tile, the row
+  // above, then the left and right columns (rows run along x)
+  __device__ void border(int h, int& hr, int& hc) const {
+    if (h < ringA) {
+      hr = 0;
+      hc = h;
+    } else if (h < 2 * ringA) {
+      hr = thv + 1;
+      hc = h - ringA;
+    } else if (h < 2 * ringA + thv) {
+      hr = 1 + (h - 2 * ringA);
+      hc = 0;
+    } else {
+      hr = 1 + (h - 2 * ringA - thv);
+      hc = twv + 1;
+    }
+  }
+  // Calls fn(hr, hc) for the ring sites this thread loads.  Each group of 16
+  // lanes takes a run of 16 consecutive border items (16 neighbouring sites
+  // of a row: one load instruction touches a few cache lines), and the runs
+  // are dealt to the waves in turn, so every wave issues the same number of
+  // border loads.
+  template <class F>
+  __device__ void for_border(F&& fn) const {
+    for (int h = (((lane >> 4) * TY + wv) << 4) + (lane & 15); h < nring; h += 64 * TY) {
+      int hr, hc;
+      border(h, hr, hc);
+      fn(hr, hc);
+    }
+  }
+};
 
-// clear the per-node particle force and the touched-node mask
-template <class S>
-__global__ void k_clear_nodes(const int32_t* __restrict__ list, const int32_t* __restrict__ nlist, S* __restrict__ gP,
-                              uint32_t* __restrict__ mask, int64_t N) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= *nlist) return;
-  const int64_t s = list[t];
-  for (int a = 0; a < 3; ++a) gP[a * N + s] = S(0);
-  mask[s >> 5] = 0u;
+// neighbour sums N_zeta = sum_i w_i rho_zeta(r + c_i) c_i from the ring
+template <class C, int TY>
+__device__ __forceinline__ void nsum_ring(const C (&ring)[4][2][TY + 2][66], int sm, int s0, int sp, int wv, int lane,
+                                          C (&NA)[3], C (&NB)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) NA[a] = NB[a] = C(0);
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
+    const int sl = cz > 0 ? sp : (cz < 0 ? sm : s0);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const C wr = weight<C>(i) * ring[sl][c][wv + 1 + cy][lane + 1 + cx];
+      C(&Nc)[3] = c == 0 ? NA : NB;
+      if (cx) Nc[0] += cx > 0 ? wr : -wr;
+      if (cy) Nc[1] += cy > 0 ? wr : -wr;
+      if (cz) Nc[2] += cz > 0 ? wr : -wr;
+    }
+  }
 }
 
 // ------------------------------------------------------------ fused path
-// Block = TY waves; wave w owns row y0+w, lane l owns column x0+l of a 64-wide
-// tile.  The block marches z over [z0, z1).  LDS ring: 4 density planes of
-// the tile plus a one-site border (the border sites are loaded by lanes of
-// every wave, a few per wave).
-template <class S, int TY, int FORCING, bool NOISE>
+// One pass per step: density ring from the pulled populations, collision of
+// every site without particle force, records at touched nodes; k_fix then
+// re-collides the touched nodes.  Best when few nodes are touched.
+template <class S, int TY, int FORCING, bool NOISE, bool HOLD>
 __global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S* __restrict__ dst_, FluidConsts<S> K,
-                                                    int tz, int tiles_x, int tiles_y, const uint32_t* __restrict__ mask,
+                                                    int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
                                                     S* __restrict__ rec, double* __restrict__ red, uint32_t* status,
                                                     long long* bad) {
   using C = S;
-  constexpr int RW = 66, RH = TY + 2;
-  __shared__ C ring[4][2][RH][RW];
+  __shared__ C ring[4][2][TY + 2][66];
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
   const int64_t plane = int64_t(nx) * ny;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const Pops<S> src = make_pops(src_, N), dst = make_pops<S>(dst_, N);
-
-  // tile of this block; consecutive block ids walk z-chunks of one column
-  // first so that the 8 XCDs each get contiguous z ranges
-  const int nchunk = (nz + tz - 1) / tz;
-  const int bid = blockIdx.x;
-  const int bz = bid % nchunk;
-  const int bxy = bid / nchunk;
-  const int bx = bxy % tiles_x, by = bxy / tiles_x;
-  const int x0 = bx * 64, y0 = by * TY, z0 = bz * tz, z1 = min(z0 + tz, nz);
-  const int twv = min(64, nx - x0), thv = min(TY, ny - y0);
-  const bool inside = lane < twv && wv < thv;
-  const int x = x0 + lane, y = y0 + wv;
-  const int ringA = twv + 2;
-  const int nring = 2 * ringA + 2 * thv;
+  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
+  const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
 
   C cur[2][19], nxt[2][19];
   double acc[5] = {0, 0, 0, 0, 0};
 
-  // density of the tile's own sites of plane zp -> ring; populations -> nxt
+  // density of the tile's own sites of plane zp -> ring; with HOLD the
+  // populations stay in registers for the collision one plane later,
+  // otherwise they are read again then (from cache)
   auto load_interior = [&](int zp_raw, int slot) {
     const int zz = wrapi(zp_raw, nz);
-    if (inside) {
+    if (T.inside) {
       pull<S, C>(src, x, y, zz, nx, ny, nz, nxt);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -390,26 +433,11 @@ __global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S
       }
     }
   };
-  // density of the one-site border of plane zp -> ring (a few lanes per wave)
   auto load_border = [&](int zp_raw, int slot) {
     const int zz = wrapi(zp_raw, nz);
-    for (int h = lane * TY + wv; h < nring; h += 64 * TY) {
-      int hr, hc;
-      if (h < ringA) {
-        hr = 0;
-        hc = h;
-      } else if (h < 2 * ringA) {
-        hr = thv + 1;
-        hc = h - ringA;
-      } else if (h < 2 * ringA + thv) {
-        hr = 1 + (h - 2 * ringA);
-        hc = 0;
-      } else {
-        hr = 1 + (h - 2 * ringA - thv);
-        hc = twv + 1;
-      }
+    T.for_border([&](int hr, int hc) {
       C hf[2][19];
-      pull<S, C>(src, wrapi(x0 - 1 + hc, nx), wrapi(y0 - 1 + hr, ny), zz, nx, ny, nz, hf);
+      pull<S, C>(src, wrapi(T.x0 - 1 + hc, nx), wrapi(T.y0 - 1 + hr, ny), zz, nx, ny, nz, hf);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         C r = hf[c][0];
@@ -417,59 +445,55 @@ __global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S
         for (int i = 1; i < 19; ++i) r += hf[c][i];
         ring[slot][c][hr][hc] = r;
       }
-    }
+    });
   };
 
-  // prologue: planes z0-1 and z0 complete, border of z0+1; cur = plane z0
+  // prologue: planes z0-1 and z0 complete, border of z0+1; plane q lives in
+  // ring slot (q - z0 + 1) & 3
+  const int z0 = T.z0, z1 = T.z1;
   load_interior(z0 - 1, 0);
   load_border(z0 - 1, 0);
   load_interior(z0, 1);
   load_border(z0, 1);
   load_border(z0 + 1, 2);
+  if (HOLD) {
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int i = 0; i < 19; ++i) cur[c][i] = nxt[c][i];
-
-  // iteration z: interior of z+1, barrier, collide z, border of z+2.  Ring
-  // slots: plane q lives in slot (q - z0 + 1) & 3; the border of z+2 goes to
-  // the slot last read in iteration z-1, which this iteration's barrier
-  // separates from it.
+      for (int i = 0; i < 19; ++i) cur[c][i] = nxt[c][i];
+  }
+  // iteration z: interior of z+1, barrier, collide z, border of z+2 (into
+  // the slot last read in iteration z-1, which this barrier separates)
   for (int z = z0; z < z1; ++z) {
     const int k = z - z0;
     load_interior(z + 1, (k + 2) & 3);
     __syncthreads();
-    if (inside) {
-      const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
-      C NA[3] = {0, 0, 0}, NB[3] = {0, 0, 0};
-#pragma unroll
-      for (int i = 1; i < 19; ++i) {
-        const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
-        const int sl = cz > 0 ? sp : (cz < 0 ? sm : s0);
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const C wr = weight<C>(i) * ring[sl][c][wv + 1 + cy][lane + 1 + cx];
-          C(&Nc)[3] = c == 0 ? NA : NB;
-          if (cx) Nc[0] += cx > 0 ? wr : -wr;
-          if (cy) Nc[1] += cy > 0 ? wr : -wr;
-          if (cz) Nc[2] += cz > 0 ? wr : -wr;
-        }
-      }
+    if (T.inside) {
+      C NA[3], NB[3];
+      nsum_ring<C, TY>(ring, k & 3, (k + 1) & 3, (k + 2) & 3, wv, lane, NA, NB);
       const int64_t s = z * plane + int64_t(y) * nx + x;
       const C gp[3] = {0, 0, 0};
-      const bool touched = mask && ((mask[s >> 5] >> (s & 31)) & 1u);
-      SiteOut<C> o = collide<C, FORCING, NOISE>(cur, NA, NB, gp, K, uint32_t(s));
-      store<S, C>(dst, uint32_t(s), cur);
-      if (touched) {
+      if (!HOLD) pull<S, C>(src, x, y, z, nx, ny, nz, cur);
+      const Macro<C> m = macro<C, FORCING>(cur, NA, NB, gp, K);
+      if (mask && ((mask[s >> 5] >> (s & 31)) & 1u)) {
         C uc[3];
-        velocity_uc<C>(o, NA, NB, K, uc);
+        coupling_velocity<C, FORCING>(m, uc);
+        C* r = rec + s * REC;
         for (int a = 0; a < 3; ++a) {
-          rec[a * N + s] = NA[a];
-          rec[(3 + a) * N + s] = NB[a];
-          rec[(6 + a) * N + s] = uc[a];
+          r[a] = NA[a];
+          r[3 + a] = NB[a];
+          r[6 + a] = uc[a];
         }
       }
+      SiteOut<C> o;
+      o.rho[0] = m.rho[0];
+      o.rho[1] = m.rho[1];
+      o.j[0] = m.j[0];
+      o.j[1] = m.j[1];
+      o.j[2] = m.j[2];
       if (!moments_ok(o)) flag_unstable(status, bad, 1u, K.step);
+      relax_site<C, FORCING, NOISE>(cur, m, K, uint32_t(s));
+      store<S, C>(dst, uint32_t(s), cur, K.nt);
       acc[0] += o.rho[0];
       acc[1] += o.rho[1];
       acc[2] += o.j[0];
@@ -477,12 +501,14 @@ __global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S
       acc[4] += o.j[2];
     }
     if (z + 2 <= z1) load_border(z + 2, (k + 3) & 3);
+    if (HOLD) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int i = 0; i < 19; ++i) cur[c][i] = nxt[c][i];
+        for (int i = 0; i < 19; ++i) cur[c][i] = nxt[c][i];
+    }
   }
-  block_sum5<TY>(acc, red + 5 * int64_t(bid));
+  block_sum5<TY>(acc, red + 5 * int64_t(T.bid));
 }
 
 // re-collide the touched nodes with the spread particle force; clears the
@@ -500,14 +526,179 @@ __global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __res
   S f[2][19], NA[3], NB[3], gp[3];
   pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
   for (int a = 0; a < 3; ++a) {
-    NA[a] = rec[a * N + s];
-    NB[a] = rec[(3 + a) * N + s];
-    gp[a] = gP[a * N + s];
-    gP[a * N + s] = S(0);
+    NA[a] = rec[s * REC + a];
+    NB[a] = rec[s * REC + 3 + a];
+    gp[a] = gP[s * GPS + a];
+    gP[s * GPS + a] = S(0);
   }
   mask[s >> 5] = 0u;
   collide<S, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s));
   store<S, S>(make_pops<S>(dst, N), uint32_t(s), f);
+}
+
+// ------------------------------------------------------------ split path
+// Pass P: density field, conservation sums, status, and the records at the
+// touched nodes (neighbour sums from the density ring, u_c).  No collision.
+template <class S, int TY, int FORCING>
+__global__ __launch_bounds__(64 * TY) void k_moments(const S* __restrict__ src_, S* __restrict__ rho, FluidConsts<S> K,
+                                                      int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
+                                                      S* __restrict__ rec, double* __restrict__ red, uint32_t* status,
+                                                      long long* bad) {
+  using C = S;
+  __shared__ C ring[4][2][TY + 2][66];
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
+  const int64_t N = K.N;
+  const int64_t plane = int64_t(nx) * ny;
+  const Pops<S> src = make_pops(src_, N);
+  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
+  const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
+  double acc[5] = {0, 0, 0, 0, 0};
+  C jn[3] = {0, 0, 0}, jc[3] = {0, 0, 0};  // raw momentum of the next / current plane
+
+  auto load_interior = [&](int zp_raw, int slot) {
+    const int zz = wrapi(zp_raw, nz);
+    if (T.inside) {
+      C f[2][19];
+      pull<S, C>(src, x, y, zz, nx, ny, nz, f);
+      C jt[3] = {0, 0, 0};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        C r, jj[3];
+        moments_pairs<C>(f[c], r, jj);
+        ring[slot][c][wv + 1][lane + 1] = r;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) jt[a] += jj[a];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) jn[a] = jt[a];
+    }
+  };
+  auto load_border = [&](int zp_raw, int slot) {
+    const int zz = wrapi(zp_raw, nz);
+    T.for_border([&](int hr, int hc) {
+      C hf[2][19];
+      pull<S, C>(src, wrapi(T.x0 - 1 + hc, nx), wrapi(T.y0 - 1 + hr, ny), zz, nx, ny, nz, hf);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        C r = hf[c][0];
+#pragma unroll
+        for (int i = 1; i < 19; ++i) r += hf[c][i];
+        ring[slot][c][hr][hc] = r;
+      }
+    });
+  };
+
+  const int z0 = T.z0, z1 = T.z1;
+  load_interior(z0 - 1, 0);
+  load_border(z0 - 1, 0);
+  load_interior(z0, 1);
+  load_border(z0, 1);
+  load_border(z0 + 1, 2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) jc[a] = jn[a];
+  for (int z = z0; z < z1; ++z) {
+    const int k = z - z0;
+    load_interior(z + 1, (k + 2) & 3);
+    __syncthreads();
+    if (T.inside) {
+      const int s0 = (k + 1) & 3;
+      const int64_t s = z * plane + int64_t(y) * nx + x;
+      SiteOut<C> o;
+      o.rho[0] = ring[s0][0][wv + 1][lane + 1];
+      o.rho[1] = ring[s0][1][wv + 1][lane + 1];
+      o.j[0] = jc[0];
+      o.j[1] = jc[1];
+      o.j[2] = jc[2];
+      rho[s] = o.rho[0];
+      rho[N + s] = o.rho[1];
+      if (mask && ((mask[s >> 5] >> (s & 31)) & 1u)) {
+        C NA[3], NB[3];
+        nsum_ring<C, TY>(ring, k & 3, s0, (k + 2) & 3, wv, lane, NA, NB);
+        const C inv = C(1) / (o.rho[0] + o.rho[1]);
+        C* r = rec + s * REC;
+        for (int a = 0; a < 3; ++a) {
+          const C gsc = -o.rho[0] * (K.G[0][0] * NA[a] + K.G[0][1] * NB[a]) -
+                        o.rho[1] * (K.G[1][0] * NA[a] + K.G[1][1] * NB[a]);
+          r[a] = NA[a];
+          r[3 + a] = NB[a];
+          r[6 + a] = (o.j[a] + C(0.5) * gsc) * inv;
+        }
+      }
+      if (!moments_ok(o)) flag_unstable(status, bad, 1u, K.step);
+      acc[0] += o.rho[0];
+      acc[1] += o.rho[1];
+      acc[2] += o.j[0];
+      acc[3] += o.j[1];
+      acc[4] += o.j[2];
+    }
+    if (z + 2 <= z1) load_border(z + 2, (k + 3) & 3);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) jc[a] = jn[a];
+  }
+  block_sum5<TY>(acc, red + 5 * int64_t(T.bid));
+}
+
+// Pass C: collision and streaming of every site, the particle force applied
+// where a particle touches; the density ring is filled from the density
+// field written by pass P (two values per site instead of 38).
+template <class S, int TY, int FORCING, bool NOISE>
+__global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_, S* __restrict__ dst_,
+                                                      const S* __restrict__ rho, FluidConsts<S> K, int tz, int tiles_x,
+                                                      int xcd, const uint32_t* __restrict__ mask, S* __restrict__ gP) {
+  using C = S;
+  __shared__ C ring[4][2][TY + 2][66];
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
+  const int64_t N = K.N;
+  const int64_t plane = int64_t(nx) * ny;
+  const Pops<S> src = make_pops(src_, N), dst = make_pops<S>(dst_, N);
+  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
+  const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
+
+  auto load_interior = [&](int zp_raw, int slot) {
+    const int64_t zz = wrapi(zp_raw, nz);
+    if (T.inside) {
+      const int64_t s = zz * plane + int64_t(y) * nx + x;
+      ring[slot][0][wv + 1][lane + 1] = rho[s];
+      ring[slot][1][wv + 1][lane + 1] = rho[N + s];
+    }
+  };
+  auto load_border = [&](int zp_raw, int slot) {
+    const int64_t zz = wrapi(zp_raw, nz);
+    T.for_border([&](int hr, int hc) {
+      const int64_t s = zz * plane + int64_t(wrapi(T.y0 - 1 + hr, ny)) * nx + wrapi(T.x0 - 1 + hc, nx);
+      ring[slot][0][hr][hc] = rho[s];
+      ring[slot][1][hr][hc] = rho[N + s];
+    });
+  };
+
+  const int z0 = T.z0, z1 = T.z1;
+  load_interior(z0 - 1, 0);
+  load_border(z0 - 1, 0);
+  load_interior(z0, 1);
+  load_border(z0, 1);
+  load_border(z0 + 1, 2);
+  for (int z = z0; z < z1; ++z) {
+    const int k = z - z0;
+    load_interior(z + 1, (k + 2) & 3);
+    __syncthreads();
+    if (T.inside) {
+      C NA[3], NB[3], f[2][19];
+      const int64_t s = z * plane + int64_t(y) * nx + x;
+      pull<S, C>(src, x, y, z, nx, ny, nz, f);
+      nsum_ring<C, TY>(ring, k & 3, (k + 1) & 3, (k + 2) & 3, wv, lane, NA, NB);
+      C gp[3] = {0, 0, 0};
+      if (mask && ((mask[s >> 5] >> (s & 31)) & 1u)) {
+        for (int a = 0; a < 3; ++a) {
+          gp[a] = gP[s * GPS + a];
+          gP[s * GPS + a] = C(0);
+        }
+      }
+      const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K);
+      relax_site<C, FORCING, NOISE>(f, m, K, uint32_t(s));
+      store<S, C>(dst, uint32_t(s), f, K.nt);
+    }
+    if (z + 2 <= z1) load_border(z + 2, (k + 3) & 3);
+  }
 }
 
 // final reductions: fluid partials [nf][5], particle partials [np][3] -> out[8]
@@ -551,6 +742,7 @@ FluidConsts<S> consts(const lbmd_ctx* h) {
   K.noise = h->p.kT > 0.0;
   K.seed = h->p.seed;
   K.step = h->step;
+  K.nt = h->nt;
   return K;
 }
 
@@ -593,43 +785,87 @@ hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out) {
   return h->p.precision == LBMD_FP64 ? export_t<double>(h, mask, out) : export_t<float>(h, mask, out);
 }
 
-template <class S, int FORCING, bool NOISE>
-static void launch_fused(lbmd_ctx* h, const S* src, S* dst, const FluidConsts<S>& K) {
-  const int tiles_x = (h->p.nx + 63) / 64;
-  const int ty = h->tile_y;
-  const int tiles_y = (h->p.ny + ty - 1) / ty;
-  const int tz = std::max(1, std::min(h->tile_z, h->p.nz));
-  const int nchunk = (h->p.nz + tz - 1) / tz;
-  const int64_t nblk = int64_t(tiles_x) * tiles_y * nchunk;
-  h->red_fluid_used = nblk;
-  const uint32_t* mask = h->np > 0 ? h->mask : nullptr;
-#define LBMD_FUSED(TY)                                                                                       \
-  hipLaunchKernelGGL((k_fused<S, TY, FORCING, NOISE>), dim3(nblk), dim3(64 * TY), 0, h->stream, src, dst, K, tz, \
-                     tiles_x, tiles_y, mask, (S*)h->rec, h->red_fluid, h->status, h->bad_step)
-  switch (ty) {
-    case 2: LBMD_FUSED(2); break;
-    case 4: LBMD_FUSED(4); break;
-    case 16: LBMD_FUSED(16); break;
-    default: LBMD_FUSED(8); break;
-  }
-#undef LBMD_FUSED
+// organisation actually used this step
+static int organisation(const lbmd_ctx* h) {
+  if (h->p.kernel != LBMD_KERNEL_AUTO) return h->p.kernel;
+  // the fused pass re-collides every touched node with scattered accesses
+  // (about 76 per node); the split passes cost one extra read of the
+  // populations.  Break-even near one touched node per 128 sites.
+  return (h->np == 0 || 8 * h->np * 128 < h->N) ? LBMD_KERNEL_FUSED : LBMD_KERNEL_TWOPASS;
 }
+
+struct Launch {
+  int tiles_x, tz, ty;
+  int64_t nblk;
+};
+// Tiling actually launched: the caller's (lbmd_set_tiling), else the
+// measured defaults on MI355X at 256^3: 4 rows x 16 planes for the fused
+// kernel (populations held in registers), 16 rows x 64 planes in XCD order
+// for the two-pass kernels.  Rows never exceed the lattice height.
+static Launch tiles(lbmd_ctx* h) {
+  if (!h->tiling_set) {
+    const bool fused = organisation_of(h) == LBMD_KERNEL_FUSED;
+    const int want = fused ? 4 : 16;
+    int ty = 2;
+    while (ty < want && ty * 2 <= h->p.ny) ty *= 2;
+    h->tile_y = ty;
+    h->tile_z = fused ? 16 : 64;
+    h->hold = 1;
+    h->xcd = fused ? 0 : 1;
+  }
+  Launch L;
+  L.tiles_x = (h->p.nx + 63) / 64;
+  L.ty = h->tile_y;
+  const int tiles_y = (h->p.ny + L.ty - 1) / L.ty;
+  L.tz = std::max(1, std::min(h->tile_z, h->p.nz));
+  L.nblk = int64_t(L.tiles_x) * tiles_y * ((h->p.nz + L.tz - 1) / L.tz);
+  return L;
+}
+
+#define LBMD_BY_TY(TY, CALL) \
+  switch (TY) {              \
+    case 2: {                \
+      constexpr int TYV = 2; \
+      CALL;                  \
+    } break;                 \
+    case 4: {                \
+      constexpr int TYV = 4; \
+      CALL;                  \
+    } break;                 \
+    case 16: {               \
+      constexpr int TYV = 16; \
+      CALL;                  \
+    } break;                 \
+    default: {               \
+      constexpr int TYV = 8; \
+      CALL;                  \
+    } break;                 \
+  }
 
 template <class S, int FORCING, bool NOISE>
 static hipError_t pass_a_t(lbmd_ctx* h) {
   const S* src = (const S*)h->f[h->cur];
   S* dst = (S*)h->f[1 - h->cur];
-  FluidConsts<S> K = consts<S>(h);
-  if (h->p.kernel == LBMD_KERNEL_FUSED) {
+  const FluidConsts<S> K = consts<S>(h);
+  const Launch L = tiles(h);
+  h->red_fluid_used = L.nblk;
+  const uint32_t* mask = h->np > 0 ? h->mask : nullptr;
+  if (organisation(h) == LBMD_KERNEL_FUSED) {
     if (hipError_t e = prof_begin(h)) return e;
-    launch_fused<S, FORCING, NOISE>(h, src, dst, K);
+    if (h->hold) {
+      LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_fused<S, TYV, FORCING, NOISE, true>), dim3(L.nblk), dim3(64 * TYV), 0,
+                                          h->stream, src, dst, K, L.tz, L.tiles_x, h->xcd, mask, (S*)h->rec, h->red_fluid,
+                                          h->status, h->bad_step));
+    } else {
+      LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_fused<S, TYV, FORCING, NOISE, false>), dim3(L.nblk), dim3(64 * TYV), 0,
+                                          h->stream, src, dst, K, L.tz, L.tiles_x, h->xcd, mask, (S*)h->rec, h->red_fluid,
+                                          h->status, h->bad_step));
+    }
     if (hipError_t e = prof_end(h)) return e;
   } else {
-    hipLaunchKernelGGL(k_density<S>, plane_grid(h), dim3(256), 0, h->stream, src, (S*)h->rho, h->p.nx, h->p.ny,
-                       h->p.nz);
-    if (h->np > 0)
-      hipLaunchKernelGGL(k_records<S>, dim3((h->flag_cap + 255) / 256), dim3(256), 0, h->stream, src,
-                         (const S*)h->rho, K, h->flag_list, h->nflag, (S*)h->rec);
+    LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_moments<S, TYV, FORCING>), dim3(L.nblk), dim3(64 * TYV), 0, h->stream, src,
+                                        (S*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (S*)h->rec, h->red_fluid, h->status,
+                                        h->bad_step));
   }
   return hipGetLastError();
 }
@@ -638,37 +874,35 @@ template <class S, int FORCING, bool NOISE>
 static hipError_t pass_b_t(lbmd_ctx* h) {
   const S* src = (const S*)h->f[h->cur];
   S* dst = (S*)h->f[1 - h->cur];
-  FluidConsts<S> K = consts<S>(h);
-  if (h->p.kernel == LBMD_KERNEL_FUSED) {
+  const FluidConsts<S> K = consts<S>(h);
+  if (organisation(h) == LBMD_KERNEL_FUSED) {
     if (h->np > 0)
       hipLaunchKernelGGL((k_fix<S, FORCING, NOISE>), dim3((h->flag_cap + 255) / 256), dim3(256), 0, h->stream, src,
                          dst, K, h->flag_list, h->nflag, (const S*)h->rec, (S*)h->gP, h->mask);
   } else {
-    dim3 g = plane_grid(h);
-    h->red_fluid_used = int64_t(g.x) * g.y * g.z;
+    const Launch L = tiles(h);
+    const uint32_t* mask = h->np > 0 ? h->mask : nullptr;
     if (hipError_t e = prof_begin(h)) return e;
-    hipLaunchKernelGGL((k_collide<S, FORCING, NOISE>), g, dim3(256), 0, h->stream, src, dst, (const S*)h->rho, K,
-                       h->np > 0 ? h->mask : nullptr, (const S*)h->gP, h->red_fluid, h->status, h->bad_step);
+    LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_collide<S, TYV, FORCING, NOISE>), dim3(L.nblk), dim3(64 * TYV), 0,
+                                        h->stream, src, dst, (const S*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (S*)h->gP));
     if (hipError_t e = prof_end(h)) return e;
-    if (h->np > 0)
-      hipLaunchKernelGGL(k_clear_nodes<S>, dim3((h->flag_cap + 255) / 256), dim3(256), 0, h->stream, h->flag_list,
-                         h->nflag, (S*)h->gP, h->mask, h->N);
+    if (h->np > 0) {
+      const int64_t words = (h->N + 31) / 32;
+      hipLaunchKernelGGL(k_zero_words, dim3((words + 255) / 256), dim3(256), 0, h->stream, h->mask, words);
+    }
   }
   return hipGetLastError();
 }
 
-template <template <class, int, bool> class F>
-struct Dispatch {};
-
-#define LBMD_DISPATCH(NAME)                                                                    \
-  hipError_t fluid_##NAME(lbmd_ctx* h) {                                                       \
-    const bool noise = h->p.kT > 0.0;                                                          \
-    if (h->p.precision == LBMD_FP64) {                                                         \
+#define LBMD_DISPATCH(NAME)                                                                      \
+  hipError_t fluid_##NAME(lbmd_ctx* h) {                                                         \
+    const bool noise = h->p.kT > 0.0;                                                            \
+    if (h->p.precision == LBMD_FP64) {                                                           \
       if (h->p.forcing == LBMD_FORCE_SHIFT) return NAME##_t<double, LBMD_FORCE_SHIFT, false>(h); \
-      return noise ? NAME##_t<double, LBMD_FORCE_PAPER, true>(h)                               \
-                   : NAME##_t<double, LBMD_FORCE_PAPER, false>(h);                             \
-    }                                                                                          \
-    if (h->p.forcing == LBMD_FORCE_SHIFT) return NAME##_t<float, LBMD_FORCE_SHIFT, false>(h);  \
+      return noise ? NAME##_t<double, LBMD_FORCE_PAPER, true>(h)                                 \
+                   : NAME##_t<double, LBMD_FORCE_PAPER, false>(h);                               \
+    }                                                                                            \
+    if (h->p.forcing == LBMD_FORCE_SHIFT) return NAME##_t<float, LBMD_FORCE_SHIFT, false>(h);    \
     return noise ? NAME##_t<float, LBMD_FORCE_PAPER, true>(h) : NAME##_t<float, LBMD_FORCE_PAPER, false>(h); \
   }
 LBMD_DISPATCH(pass_a)
@@ -680,5 +914,7 @@ hipError_t finalize_step(lbmd_ctx* h) {
                      h->red_part_used, h->red_out, h->nflag);
   return hipGetLastError();
 }
+
+int organisation_of(const lbmd_ctx* h) { return organisation(h); }
 
 }  // namespace lbmd

@@ -107,6 +107,7 @@ struct FluidConsts {
   int noise;    // kT > 0
   uint64_t seed;
   int64_t step;
+  int nt;  // non-temporal hint on the population stores
 };
 
 }  // namespace lbmd
@@ -125,14 +126,18 @@ struct lbmd_ctx {
   int cur = 0;
   void* rho = nullptr;  // [2][N] density field (two-pass kernel)
   int tile_y = 8, tile_z = 16;
+  int hold = 1;  // fused kernel keeps the next plane's populations in registers
+  int xcd = 0;   // XCD-aware block order of the z-march kernels
+  int nt = 1;    // non-temporal population stores
+  bool tiling_set = false;  // false: per-organisation defaults (see tiles())
 
   // particle coupling
   uint32_t* mask = nullptr;  // one bit per site: touched by a particle
   int32_t* flag_list = nullptr;
   int32_t* nflag = nullptr;  // device counter
   int64_t flag_cap = 0;
-  void* rec = nullptr;  // [9][N]: N_A(3), N_B(3), u_c(3) at touched nodes
-  void* gP = nullptr;   // [3][N]: particle force density accumulated at nodes
+  void* rec = nullptr;  // [N][16]: N_A(3), N_B(3), u_c(3) at touched nodes
+  void* gP = nullptr;   // [N][4]: particle force density accumulated at nodes
 
   // particles (always float64)
   int64_t np = 0, np_cap = 0;
@@ -184,6 +189,7 @@ hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out_dev);
 hipError_t fluid_pass_a(lbmd_ctx* h);  // moments, SC force, records (+ fused collide)
 hipError_t fluid_pass_b(lbmd_ctx* h);  // collision with the particle force
 hipError_t finalize_step(lbmd_ctx* h);  // reductions, counters
+int organisation_of(const lbmd_ctx* h);  // LBMD_KERNEL_FUSED or _TWOPASS this step
 // launchers (lbmd_particles.hip)
 hipError_t particles_begin(lbmd_ctx* h);  // reduction terms, half kick, drift, flags, cells
 hipError_t particles_forces(lbmd_ctx* h); // coupling + conservative forces, spread

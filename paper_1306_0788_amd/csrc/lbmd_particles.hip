@@ -33,6 +33,7 @@ struct PartArgs {
   PairParams pp;
   int ncell[3];
   int use_cells;
+  int build_list;  // append touched nodes to the compact list (fused organisation)
 };
 
 __device__ __forceinline__ double wrapd(double x, double L) {
@@ -113,22 +114,35 @@ __global__ __launch_bounds__(256) void k_begin(PartArgs A, double* __restrict__ 
       rank_of[p] = atomicAdd(&cell_count[c], 1);
     }
   }
-  // mark the 8 nodes; append the ones this thread marked first
-  for (int k = 0; k < 8; ++k) {
-    bool fresh = false;
-    if (valid) {
+  // mark the 8 nodes; with build_list, append the ones this thread marked
+  // first to the compact list with one counter update per wave
+  uint32_t fresh = 0;  // bit k: node k newly marked by this thread
+  if (valid)
+    for (int k = 0; k < 8; ++k) {
       const uint32_t bit = 1u << (node[k] & 31);
-      const uint32_t old = atomicOr(&mask[node[k] >> 5], bit);
-      fresh = !(old & bit);
+      if (A.build_list) {
+        const uint32_t old = atomicOr(&mask[node[k] >> 5], bit);
+        if (!(old & bit)) fresh |= 1u << k;
+      } else {
+        atomicOr(&mask[node[k] >> 5], bit);
+      }
     }
-    const unsigned long long b = __ballot(fresh);
-    if (b) {
-      const int leader = __ffsll((long long)b) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(nlist, __popcll(b));
-      base = __shfl(base, leader, 64);
-      if (fresh) list[base + __popcll(b & ((1ull << lane) - 1ull))] = int32_t(node[k]);
+  if (A.build_list) {
+    // exclusive prefix of the fresh counts over the wave
+    const int mine = __popc(fresh);
+    int incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += t;
     }
+    const int total = __shfl(incl, 63, 64);
+    int base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(nlist, total);
+    base = __shfl(base, 63, 64);
+    int slot = base + incl - mine;
+    for (int k = 0; k < 8; ++k)
+      if (fresh & (1u << k)) list[slot++] = int32_t(node[k]);
   }
   for (int a = 0; a < 3; ++a) mom[a] = wave_sum(mom[a]);
   if (lane == 0)
@@ -206,9 +220,10 @@ __global__ __launch_bounds__(256) void k_forces(PartArgs A, const double* __rest
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ cell_of,
                                                 const int32_t* __restrict__ bstart, const int32_t* __restrict__ bnbr,
                                                 uint32_t* status, long long* bad) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= A.np) return;
-  const int64_t N = A.N;
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= A.np) return;
+  // particles in cell order: neighbouring threads share cells and nodes
+  const int64_t p = A.use_cells ? int64_t(perm[tid]) : tid;
   const int t = type[p];
   const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
   int64_t node[8];
@@ -219,10 +234,11 @@ __global__ __launch_bounds__(256) void k_forces(PartArgs A, const double* __rest
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int64_t s = node[k];
+    const C* r = rec + s * 16;
     for (int a = 0; a < 3; ++a) {
-      gA[a] += W[k] * 3.0 * double(rec[a * N + s]);
-      gB[a] += W[k] * 3.0 * double(rec[(3 + a) * N + s]);
-      up[a] += W[k] * double(rec[(6 + a) * N + s]);
+      gA[a] += W[k] * 3.0 * double(r[a]);
+      gB[a] += W[k] * 3.0 * double(r[3 + a]);
+      up[a] += W[k] * double(r[6 + a]);
     }
   }
   double R[4] = {0, 0, 0, 0};
@@ -243,13 +259,19 @@ __global__ __launch_bounds__(256) void k_forces(PartArgs A, const double* __rest
     const int lo[3] = {A.ncell[0] >= 3 ? -1 : 0, A.ncell[1] >= 3 ? -1 : 0, A.ncell[2] >= 3 ? -1 : 0};
     const int hi[3] = {A.ncell[0] >= 3 ? 1 : 0, A.ncell[1] >= 3 ? 1 : 0, A.ncell[2] >= 3 ? 1 : 0};
     const double qp = A.T.charge[t];
+    // all cell ranges first (independent loads), then the pairs
+    int rb[27], re[27], nr = 0;
     for (int dz = lo[2]; dz <= hi[2]; ++dz)
       for (int dy = lo[1]; dy <= hi[1]; ++dy)
         for (int dx = lo[0]; dx <= hi[0]; ++dx) {
           const int nc = (wrapi(cz + dz, A.ncell[2]) * A.ncell[1] + wrapi(cy + dy, A.ncell[1])) * A.ncell[0] +
                          wrapi(cx + dx, A.ncell[0]);
-          const int b = cell_start[nc], e = cell_start[nc + 1];
-          for (int jj = b; jj < e; ++jj) {
+          rb[nr] = cell_start[nc];
+          re[nr] = cell_start[nc + 1];
+          ++nr;
+        }
+    for (int rr = 0; rr < nr; ++rr) {
+          for (int jj = rb[rr]; jj < re[rr]; ++jj) {
             const int q = perm[jj];
             if (q == p) continue;
             double d[3];
@@ -266,7 +288,7 @@ __global__ __launch_bounds__(256) void k_forces(PartArgs A, const double* __rest
               add_radial(qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) / r2, d, r, Fp);
             }
           }
-        }
+    }
   }
   if (A.pp.fene_on && bstart) {
     for (int jj = bstart[p]; jj < bstart[p + 1]; ++jj) {
@@ -290,7 +312,7 @@ __global__ __launch_bounds__(256) void k_forces(PartArgs A, const double* __rest
   // momentum returned to the fluid by the same interpolation
 #pragma unroll
   for (int k = 0; k < 8; ++k)
-    for (int a = 0; a < 3; ++a) atomicAdd(&gP[a * N + node[k]], C(-W[k] * fc[a]));
+    for (int a = 0; a < 3; ++a) atomicAdd(&gP[node[k] * 4 + a], C(-W[k] * fc[a]));
 }
 
 __global__ void k_end(PartArgs A, const double* __restrict__ x, double* __restrict__ v, const double* __restrict__ F,
@@ -323,6 +345,7 @@ static PartArgs args(const lbmd_ctx* h) {
   A.pp = h->pair;
   for (int a = 0; a < 3; ++a) A.ncell[a] = h->ncell[a];
   A.use_cells = (h->pair.wca_on || h->pair.dh_on) ? 1 : 0;
+  A.build_list = organisation_of(h) == LBMD_KERNEL_FUSED ? 1 : 0;
   return A;
 }
 

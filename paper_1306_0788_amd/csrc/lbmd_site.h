@@ -53,113 +53,178 @@ struct SiteOut {
 template <class C>
 __device__ __forceinline__ C csqrt(C v) { return sqrt(v); }
 
-// f[2][19]: post-streaming populations at the site (overwritten with the
-// post-collision values).  NA, NB: neighbour sums N_zeta = sum_i w_i
-// rho_zeta(r+c_i) c_i.  gp: total particle force density at the node.
-template <class C, int FORCING, bool NOISE>
-__device__ __forceinline__ SiteOut<C> collide(C (&f)[2][19], const C (&NA)[3], const C (&NB)[3],
-                                              const C (&gp)[3], const FluidConsts<C>& K, uint32_t site) {
-  SiteOut<C> o;
-  C jc[2][3];
+// Moments of one component from opposite-pair sums and differences.
+template <class C>
+__device__ __forceinline__ void moments_pairs(const C (&f)[19], C& rho, C (&j)[3]) {
+  C sp[9], dp[9];
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    C r = f[c][0], jx = 0, jy = 0, jz = 0;
-#pragma unroll
-    for (int i = 1; i < 19; ++i) {
-      r += f[c][i];
-      if (D3Q19::cx[i]) jx += D3Q19::cx[i] > 0 ? f[c][i] : -f[c][i];
-      if (D3Q19::cy[i]) jy += D3Q19::cy[i] > 0 ? f[c][i] : -f[c][i];
-      if (D3Q19::cz[i]) jz += D3Q19::cz[i] > 0 ? f[c][i] : -f[c][i];
-    }
-    o.rho[c] = r;
-    jc[c][0] = jx;
-    jc[c][1] = jy;
-    jc[c][2] = jz;
+  for (int p = 0; p < 9; ++p) {
+    sp[p] = f[2 * p + 1] + f[2 * p + 2];
+    dp[p] = f[2 * p + 1] - f[2 * p + 2];
   }
-  o.j[0] = jc[0][0] + jc[1][0];
-  o.j[1] = jc[0][1] + jc[1][1];
-  o.j[2] = jc[0][2] + jc[1][2];
-  const C rt = o.rho[0] + o.rho[1];
-  const C inv_rt = C(1) / rt;
+  rho = f[0] + (((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]))) + sp[8];
+  // pair velocities (+c of each pair): x, y, z, (1,1,0), (1,-1,0), (1,0,1),
+  // (1,0,-1), (0,1,1), (0,1,-1)
+  j[0] = ((dp[0] + dp[3]) + (dp[4] + dp[5])) + dp[6];
+  j[1] = ((dp[1] + dp[3]) - (dp[4] - dp[7])) + dp[8];
+  j[2] = ((dp[2] + dp[5]) - (dp[6] - dp[7])) - dp[8];
+}
+
+// BGK relaxation of one component towards f^eq(rho, u) (Appendix, Eq. feq)
+// plus, if FORCE, the paper's forcing source term with all eigenvalues
+// -1/tau (Appendix, last equations), which reads
+//   fpre w_i [3 (c_i - u).g + 9 (c_i.u)(c_i.g)],  fpre = 1 - omega/2.
+// Opposite velocities share the even part of both terms and flip the odd
+// part, so each pair costs one evaluation.
+template <class C, bool FORCE>
+__device__ __forceinline__ void relax(C (&f)[19], C rho, const C (&u)[3], const C (&g)[3], C om) {
+  const C usq = C(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const C keep = C(1) - om;
+  const C fpre = C(1) - C(0.5) * om;
+  const C ug = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+  // rest population
+  {
+    const C w = weight<C>(0);
+    C e = om * (w * rho * (C(1) - usq));
+    if (FORCE) e += fpre * w * (C(-3) * ug);
+    f[0] = keep * f[0] + e;
+  }
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    const int i = 2 * p + 1;
+    const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
+    const C w = weight<C>(i);
+    C cu = 0, cg = 0;
+    if (cx) { cu += cx > 0 ? u[0] : -u[0]; cg += cx > 0 ? g[0] : -g[0]; }
+    if (cy) { cu += cy > 0 ? u[1] : -u[1]; cg += cy > 0 ? g[1] : -g[1]; }
+    if (cz) { cu += cz > 0 ? u[2] : -u[2]; cg += cz > 0 ? g[2] : -g[2]; }
+    const C wr = w * rho;
+    C even = om * (wr * (C(1) - usq + C(4.5) * cu * cu));
+    C odd = om * (C(3) * wr * cu);
+    if (FORCE) {
+      const C fw = fpre * w;
+      even += fw * (C(9) * cu * cg - C(3) * ug);
+      odd += fw * (C(3) * cg);
+    }
+    f[i] = keep * f[i] + (even + odd);
+    f[i + 1] = keep * f[i + 1] + (even - odd);
+  }
+}
+
+// Macroscopic part of the collision: densities, raw momentum, forces and
+// the equilibrium velocity of each component.
+template <class C>
+struct Macro {
+  C rho[2];
+  C j[3];      // raw momentum sum_zeta sum_i f c_i
+  C u[2][3];   // equilibrium velocity per component
+  C g[2][3];   // total force density per component
+  C inv_rt;
+};
+
+// NA, NB: neighbour sums N_zeta = sum_i w_i rho_zeta(r+c_i) c_i;
+// gp: total particle force density at the node
+template <class C, int FORCING>
+__device__ __forceinline__ Macro<C> macro(const C (&f)[2][19], const C (&NA)[3], const C (&NB)[3],
+                                          const C (&gp)[3], const FluidConsts<C>& K) {
+  Macro<C> m;
+  C jc[2][3];
+  moments_pairs<C>(f[0], m.rho[0], jc[0]);
+  moments_pairs<C>(f[1], m.rho[1], jc[1]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) m.j[a] = jc[0][a] + jc[1][a];
+  m.inv_rt = C(1) / (m.rho[0] + m.rho[1]);
   // Shan-Chen force g_zeta = -rho_zeta sum_zeta' G N_zeta' (Sec. 2, Eq.
   // SCforce) plus the particle force split by mass fraction
-  C g[2][3];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const C frac = o.rho[c] * inv_rt;
+    const C frac = m.rho[c] * m.inv_rt;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      g[c][a] = -o.rho[c] * (K.G[c][0] * NA[a] + K.G[c][1] * NB[a]) + frac * gp[a];
+      m.g[c][a] = -m.rho[c] * (K.G[c][0] * NA[a] + K.G[c][1] * NB[a]) + frac * gp[a];
   }
-  C ueq[2][3];
   if (FORCING == LBMD_FORCE_PAPER) {
+    // barycentric velocity with half the total force (Appendix, u and
+    // momentum_definition)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const C u = (o.j[a] + C(0.5) * (g[0][a] + g[1][a])) * inv_rt;
-      ueq[0][a] = u;
-      ueq[1][a] = u;
+      const C u = (m.j[a] + C(0.5) * (m.g[0][a] + m.g[1][a])) * m.inv_rt;
+      m.u[0][a] = u;
+      m.u[1][a] = u;
     }
   } else {
-    const C den = C(1) / (o.rho[0] * K.omega[0] + o.rho[1] * K.omega[1]);
+    // velocity shift: 1/tau-weighted common velocity shifted by
+    // tau_zeta g_zeta / rho_zeta
+    const C den = C(1) / (m.rho[0] * K.omega[0] + m.rho[1] * K.omega[1]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const C up = (jc[0][a] * K.omega[0] + jc[1][a] * K.omega[1]) * den;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) ueq[c][a] = up + K.tau[c] * g[c][a] / o.rho[c];
+      for (int c = 0; c < 2; ++c) m.u[c][a] = up + K.tau[c] * m.g[c][a] / m.rho[c];
     }
   }
-  // fluctuations: 3 shared momentum normals (opposite sign for A and B), 15
-  // per component for the bulk, shear and kinetic modes
-  C z[36];
-  C sc[2] = {0, 0}, sm = 0;
+  return m;
+}
+
+// velocity seen by the particles, u_c = (j + sum_zeta g_SC,zeta / 2) / rho,
+// when m was built without particle force (for the paper's forcing it is
+// the equilibrium velocity itself)
+template <class C, int FORCING>
+__device__ __forceinline__ void coupling_velocity(const Macro<C>& m, C (&uc)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    uc[a] = FORCING == LBMD_FORCE_PAPER ? m.u[0][a] : (m.j[a] + C(0.5) * (m.g[0][a] + m.g[1][a])) * m.inv_rt;
+}
+
+// Relaxation of both components (and fluctuations when NOISE).
+template <class C, int FORCING, bool NOISE>
+__device__ __forceinline__ void relax_site(C (&f)[2][19], const Macro<C>& m, const FluidConsts<C>& K,
+                                           uint32_t site) {
+  relax<C, FORCING == LBMD_FORCE_PAPER>(f[0], m.rho[0], m.u[0], m.g[0], K.omega[0]);
+  relax<C, FORCING == LBMD_FORCE_PAPER>(f[1], m.rho[1], m.u[1], m.g[1], K.omega[1]);
   if (NOISE) {
+    // fluctuations (Appendix, Eq. MODES): 3 shared momentum normals with
+    // opposite sign for A and B, 15 per component for the bulk, shear and
+    // kinetic modes; amplitude sqrt(rho (kT/c_s^2) (1-(1+lambda)^2) / b_k)
+    // per mode, mapped back with w_i e_ki
+    C z[36];
 #pragma unroll
     for (int b = 0; b < 9; ++b) normals4<C>(K.seed, K.step, site, b, 0, &z[4 * b]);
     const C om = K.omega[0];
-    const C relax = C(1) - (C(1) - om) * (C(1) - om);
-    const C t = C(3) * K.kT * relax;  // (kT / c_s^2) (1 - (1+lambda)^2)
-    sc[0] = csqrt(fmax(o.rho[0], C(0)) * t);
-    sc[1] = csqrt(fmax(o.rho[1], C(0)) * t);
-    sm = csqrt(fmax(o.rho[0] * o.rho[1] * inv_rt, C(0)) * t);
-  }
+    const C t = C(3) * K.kT * (C(1) - (C(1) - om) * (C(1) - om));
+    const C sc[2] = {csqrt(fmax(m.rho[0], C(0)) * t), csqrt(fmax(m.rho[1], C(0)) * t)};
+    const C sm = csqrt(fmax(m.rho[0] * m.rho[1] * m.inv_rt, C(0)) * t);
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const C om = K.omega[c];
-    const C ux = ueq[c][0], uy = ueq[c][1], uz = ueq[c][2];
-    const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
-    const C gx = g[c][0], gy = g[c][1], gz = g[c][2];
-    const C ug = ux * gx + uy * gy + uz * gz;
-    const C fpre = C(1) - C(0.5) * om;  // (2 + lambda)/2 with lambda = -1/tau
-    // noise amplitudes per mode: sqrt(rho (kT/c_s^2) relax / b_k) r_k
-    C a[19];
-    if (NOISE) {
+    for (int c = 0; c < 2; ++c) {
+      C a[19];
 #pragma unroll
-      for (int k = 1; k < 4; ++k)
-        a[k] = (c == 0 ? sm : -sm) * z[k - 1] * C(6) / csqrt(C(mode_b36(k)));
+      for (int k = 1; k < 4; ++k) a[k] = (c == 0 ? sm : -sm) * z[k - 1] * C(6) / csqrt(C(mode_b36(k)));
 #pragma unroll
       for (int k = 4; k < 19; ++k) a[k] = sc[c] * z[3 + 15 * c + (k - 4)] * C(6) / csqrt(C(mode_b36(k)));
-    }
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
-      const C cu = C(cx) * ux + C(cy) * uy + C(cz) * uz;
-      const C w = weight<C>(i);
-      const C feq = w * o.rho[c] * (C(1) + C(3) * cu + C(4.5) * cu * cu - usq);
-      C fn = f[c][i] + om * (feq - f[c][i]);
-      if (FORCING == LBMD_FORCE_PAPER) {
-        const C cg = C(cx) * gx + C(cy) * gy + C(cz) * gz;
-        fn += fpre * w * (C(3) * (cg - ug) + C(9) * cu * cg);
-      }
-      if (NOISE) {
+      for (int i = 0; i < 19; ++i) {
         C s = 0;
 #pragma unroll
         for (int k = 1; k < 19; ++k)
           if (mode_e(k, i) != 0) s += C(mode_e(k, i)) * a[k];
-        fn += w * s;
+        f[c][i] += weight<C>(i) * s;
       }
-      f[c][i] = fn;
     }
   }
+}
+
+// whole collision at one site (f overwritten with the post-collision values)
+template <class C, int FORCING, bool NOISE>
+__device__ __forceinline__ SiteOut<C> collide(C (&f)[2][19], const C (&NA)[3], const C (&NB)[3],
+                                              const C (&gp)[3], const FluidConsts<C>& K, uint32_t site) {
+  const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K);
+  relax_site<C, FORCING, NOISE>(f, m, K, site);
+  SiteOut<C> o;
+  o.rho[0] = m.rho[0];
+  o.rho[1] = m.rho[1];
+  o.j[0] = m.j[0];
+  o.j[1] = m.j[1];
+  o.j[2] = m.j[2];
   return o;
 }
 

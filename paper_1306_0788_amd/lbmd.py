@@ -15,7 +15,7 @@ LIBPATH = os.path.join(_HERE, "liblbmd.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 FORCE_PAPER, FORCE_SHIFT = 0, 1
-KERNEL_FUSED, KERNEL_TWOPASS = 0, 1
+KERNEL_FUSED, KERNEL_TWOPASS, KERNEL_AUTO = 0, 1, 2
 RHO, U, POP = 1, 2, 4
 PAIR_WCA, PAIR_DH, BOND_FENE = 0, 1, 2
 MAX_TYPES = 8
@@ -74,7 +74,7 @@ def load():
     L.lbmd_get_step.restype = ctypes.c_int64
     L.lbmd_last_error.argtypes = [H]
     L.lbmd_last_error.restype = ctypes.c_char_p
-    L.lbmd_set_tiling.argtypes = [H, ctypes.c_int32, ctypes.c_int32]
+    L.lbmd_set_tiling.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.lbmd_kernel_timing.argtypes = [H, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
         if name not in ("lbmd_get_step", "lbmd_last_error"):
@@ -97,7 +97,7 @@ def _f64(a, shape=None):
 class Sim:
     """One simulation handle.  Parameters follow lbmd_params."""
 
-    def __init__(self, shape, precision=FP32, forcing=FORCE_PAPER, kernel=KERNEL_FUSED, tau=(1.0, 1.0),
+    def __init__(self, shape, precision=FP32, forcing=FORCE_PAPER, kernel=KERNEL_AUTO, tau=(1.0, 1.0),
                  G=((0.0, 1.6), (1.6, 0.0)), gamma=0.0, kappa=(0.0, 0.0), mass=1.0, kT=0.0, seed=0,
                  check_every=0, rho_init=None, stream=None):
         L = load()
@@ -160,8 +160,9 @@ class Sim:
         b = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
         self._check(load().lbmd_set_bonds(self._h, b.shape[0], b.ctypes.data_as(_I32)))
 
-    def set_tiling(self, tile_y, tile_z):
-        self._check(load().lbmd_set_tiling(self._h, tile_y, tile_z))
+    def set_tiling(self, tile_y, tile_z, hold=1, xcd=0, nt=1):
+        flags = (1 if hold else 0) | (2 if xcd else 0) | (4 if nt else 0)
+        self._check(load().lbmd_set_tiling(self._h, tile_y, tile_z, flags))
 
     def step(self, n=1):
         return self._check(load().lbmd_step(self._h, n))

@@ -77,9 +77,11 @@ def test_ragged_shapes(shape, kernel):
     compare(c, g, o, 1e-11, 1e-11, "ragged")
 
 
-@pytest.mark.parametrize("tiling", [(2, 1), (4, 3), (8, 5), (16, 40)])
-def test_tilings_agree(tiling):
-    c = Case((37, 29, 23), FP64, PAPER, FUSED, G=1.3, gamma=0.7, npart=40, vel_amp=0.02, tiling=tiling)
+@pytest.mark.parametrize("tiling", [(2, 1, 1, 1), (4, 3, 0, 1), (8, 5, 1, 0), (8, 7, 0, 0), (16, 40, 1, 1),
+                                    (16, 2, 0, 1)])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_tilings_agree(tiling, kernel):
+    c = Case((37, 29, 23), FP64, PAPER, kernel, G=1.3, gamma=0.7, npart=40, vel_amp=0.02, tiling=tiling)
     g, o = run_pair(c, 3)
     compare(c, g, o, 1e-11, 1e-11, "tiling %s" % (tiling,))
 
