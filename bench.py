@@ -40,10 +40,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, nsites, s_bytes):
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+def measured_traffic(kernel_name, workload):
+    """HBM bytes per launch of the timed kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(PROFILE_DIR, "k_fused_%s_counters.md" % workload)
+    path = os.path.join(PROFILE_DIR, "%s_%s_counters.md" % (kernel_name, workload))
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -107,6 +107,30 @@ def cpu_baseline(workload, target_s=15.0):
                       % (steps, workload, len(x))}
 
 
+def copy_calibration():
+    """A plain elementwise copy kernel (torch.mul by 1) over 2 GiB of float32:
+    the reference for scaling the FETCH_SIZE / WRITE_SIZE counters and for the
+    copy bandwidth this device reaches in practice."""
+    import torch
+    torch.cuda.set_device(0)
+    n = 512 * 1024 * 1024
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"copy_kernel_bytes_read": n * 4, "copy_kernel_bytes_written": n * 4,
+                      "ms": round(ms, 4), "GBs_read_plus_write": round(2 * n * 4 / ms / 1e6, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,7 +142,12 @@ def main():
     ap.add_argument("--kernel", choices=["auto", "fused", "twopass"], default="auto")
     ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("TILE_Y", "TILE_Z"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 2 GiB copy kernel used to calibrate the byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the path shards by z-slabs across GPUs, "
               "which is not built); use --gpus 1", file=sys.stderr)
@@ -135,6 +164,7 @@ def main():
     kernel = {"auto": lbmd.KERNEL_AUTO, "fused": lbmd.KERNEL_FUSED, "twopass": lbmd.KERNEL_TWOPASS}[args.kernel]
     print("bench: setting up %s" % args.workload, file=sys.stderr, flush=True)
     sim, w, npart = setup(args.workload, stream.cuda_stream, kernel, args.tiling)
+    sim_org = sim.organisation()
     N = int(np.prod(w["shape"]))
     s_bytes = 4 if w["precision"] == "fp32" else 8
 
@@ -163,7 +193,8 @@ def main():
     alg_bytes = 76 * s_bytes * N
     kavg_s = kms * 1e-3 / max(launches, 1)
     achieved = alg_bytes / kavg_s / 1e9
-    traffic = measured_traffic(args.workload, N, s_bytes)
+    kname = "k_fused" if sim_org == lbmd.KERNEL_FUSED else "k_collide"
+    traffic = measured_traffic(kname, args.workload)
     line = {
         "metric": "MLUPS (2-component D3Q19 Shan-Chen + coupled particles, one full step)",
         "value": round(mlups, 2),
@@ -178,11 +209,12 @@ def main():
         "dtype": "f32" if s_bytes == 4 else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": list(w["shape"]), "particles": npart,
-                   "forcing": w["forcing"], "kT": w["kT"], "kernel": args.kernel,
+                   "forcing": w["forcing"], "kT": w["kT"],
+                   "kernel": "fused" if sim_org == lbmd.KERNEL_FUSED else "twopass",
                    "particle_updates_per_s": round(npart * args.steps / (ms * 1e-3), 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_fused" if kernel == lbmd.KERNEL_FUSED else "k_collide",
+                     "traffic": traffic, "kernel": kname,
                      "kernel_ms_avg": round(kavg_s * 1e3, 5), "bytes_per_site": 76 * s_bytes},
     }
     sim.close()

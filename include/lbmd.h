@@ -221,6 +221,11 @@ int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z, int32_t flags
    number.  Waits.  Errors: LBMD_EDEVICE. */
 int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t* launches);
 
+/* Organisation the next step will use: LBMD_KERNEL_FUSED or
+   LBMD_KERNEL_TWOPASS (resolves LBMD_KERNEL_AUTO); negative on a NULL
+   handle. */
+int lbmd_organisation(lbmd_handle h);
+
 #ifdef __cplusplus
 }
 #endif

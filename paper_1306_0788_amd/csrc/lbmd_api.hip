@@ -535,6 +535,8 @@ int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z, int32_t flags
   return LBMD_OK;
 }
 
+int lbmd_organisation(lbmd_handle h) { return h ? organisation_of(h) : LBMD_EINVAL; }
+
 int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t* launches) {
   if (!h) return LBMD_EINVAL;
   HIPCHECK(h, hipStreamSynchronize(h->stream));

@@ -23,7 +23,7 @@ MAX_TYPES = 8
 EXPORTS = ["lbmd_create", "lbmd_destroy", "lbmd_set_particles", "lbmd_set_particle_types",
            "lbmd_set_pair_potential", "lbmd_set_bonds", "lbmd_step", "lbmd_sync", "lbmd_get_fields",
            "lbmd_get_particles", "lbmd_set_populations", "lbmd_reductions", "lbmd_get_step",
-           "lbmd_last_error", "lbmd_set_tiling", "lbmd_kernel_timing"]
+           "lbmd_last_error", "lbmd_set_tiling", "lbmd_kernel_timing", "lbmd_organisation"]
 
 
 class LbmdError(RuntimeError):
@@ -76,6 +76,7 @@ def load():
     L.lbmd_last_error.restype = ctypes.c_char_p
     L.lbmd_set_tiling.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.lbmd_kernel_timing.argtypes = [H, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64)]
+    L.lbmd_organisation.argtypes = [H]
     for name in EXPORTS:
         if name not in ("lbmd_get_step", "lbmd_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -226,6 +227,10 @@ class Sim:
         n = ctypes.c_int64()
         self._check(load().lbmd_kernel_timing(self._h, int(enable), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def organisation(self):
+        """KERNEL_FUSED or KERNEL_TWOPASS: the organisation of the next step."""
+        return load().lbmd_organisation(self._h)
 
     @property
     def step_index(self):
