@@ -15,7 +15,8 @@ dataset):
     to an earlier one (periodic minimum image);
   * chains: random walks of fixed bond length 0.97 started at uniform points,
     each new bead rejected while closer than `min_dist` to a bead already
-    placed that is not its bonded predecessor.
+    placed that is not its bonded predecessor; a chain that gets stuck is
+    removed and restarted elsewhere.
 """
 import math
 
@@ -66,7 +67,7 @@ def initial_densities(shape, seed, amp=0.01, mean=1.0):
 
 
 def _too_close_grid(points, box, min_dist):
-    """Cell hash for rejection sampling; returns (insert, check) closures."""
+    """Cell hash for rejection sampling; returns (insert, check, remove)."""
     cell = max(min_dist, 1e-9)
     ncell = [max(1, int(math.floor(b / cell))) for b in box]
     grid = {}
@@ -76,6 +77,9 @@ def _too_close_grid(points, box, min_dist):
 
     def insert(i, p):
         grid.setdefault(key(p), []).append(i)
+
+    def remove(i, p):
+        grid[key(p)].remove(i)
 
     def check(p, ignore=()):
         if min_dist <= 0.0:
@@ -95,7 +99,7 @@ def _too_close_grid(points, box, min_dist):
                             return True
         return False
 
-    return insert, check
+    return insert, check, remove
 
 
 def free_particles(n, shape, seed, min_dist=0.0, max_tries=1000):
@@ -105,7 +109,7 @@ def free_particles(n, shape, seed, min_dist=0.0, max_tries=1000):
     if min_dist <= 0.0:
         return g.random((n, 3)) * box
     pts = np.zeros((n, 3))
-    insert, check = _too_close_grid(pts, box, min_dist)
+    insert, check, _ = _too_close_grid(pts, box, min_dist)
     for i in range(n):
         for _ in range(max_tries):
             p = g.random(3) * box
@@ -118,34 +122,51 @@ def free_particles(n, shape, seed, min_dist=0.0, max_tries=1000):
     return pts
 
 
-def chains(nchains, nbeads, shape, seed, bond=0.97, min_dist=0.9, max_tries=200):
+def chains(nchains, nbeads, shape, seed, bond=0.97, min_dist=0.9, max_tries=200, max_restarts=100):
     """Random-walk chains.  Returns positions [nchains*nbeads][3] (wrapped into
-    the box) and bonds [nchains*(nbeads-1)][2] (int32)."""
+    the box) and bonds [nchains*(nbeads-1)][2] (int32).  A chain whose next
+    bead cannot be placed is removed and started again elsewhere, so no two
+    non-bonded beads end up closer than min_dist."""
     g = rng(seed + 2000003)
     box = np.asarray(shape, dtype=np.float64)
     n = nchains * nbeads
     pts = np.zeros((n, 3))
-    insert, check = _too_close_grid(pts, box, min_dist)
+    insert, check, remove = _too_close_grid(pts, box, min_dist)
     bonds = []
     for c in range(nchains):
         base = c * nbeads
-        for _ in range(max_tries):
-            p = g.random(3) * box
-            if not check(p):
-                break
-        pts[base] = p
-        insert(base, p)
-        for b in range(1, nbeads):
-            prev = pts[base + b - 1]
+        for _ in range(max_restarts):
+            placed = 0
+            p = None
             for _ in range(max_tries):
-                d = g.normal(size=3)
-                d *= bond / np.linalg.norm(d)
-                p = np.mod(prev + d, box)
-                if not check(p, ignore=(base + b - 1,)):
+                p = g.random(3) * box
+                if not check(p):
                     break
-            pts[base + b] = p
-            insert(base + b, p)
-            bonds.append((base + b - 1, base + b))
+            else:
+                continue
+            pts[base] = p
+            insert(base, p)
+            placed = 1
+            for b in range(1, nbeads):
+                prev = pts[base + b - 1]
+                for _ in range(max_tries):
+                    d = g.normal(size=3)
+                    d *= bond / np.linalg.norm(d)
+                    p = np.mod(prev + d, box)
+                    if not check(p, ignore=(base + b - 1,)):
+                        break
+                else:
+                    break
+                pts[base + b] = p
+                insert(base + b, p)
+                placed += 1
+            if placed == nbeads:
+                break
+            for b in range(placed):
+                remove(base + b, pts[base + b])
+        else:
+            raise RuntimeError("could not place chain %d" % c)
+        bonds.extend((base + b - 1, base + b) for b in range(1, nbeads))
     return pts, np.asarray(bonds, dtype=np.int32).reshape(-1, 2)
 
 

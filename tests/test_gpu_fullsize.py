@@ -1,0 +1,127 @@
+"""GPU checks at the full 256^3 size, in the launch configuration bench.py
+times, against the oracle evaluated one output at a time (sampled sites
+and particles), plus the onset of the Shan-Chen instability at G = 1.8.
+
+The oracle cannot run a whole 256^3 step in test time, so after one GPU step
+from the initial state it evaluates, for each sampled site, the collision of
+the 19 upstream sites that stream into it (with the particle force at those
+nodes), and for each sampled particle its coupling and conservative forces.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1306_0788_amd import lbmd, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(name):
+    import bench
+    w = workloads.WORKLOADS[name]
+    shape = w["shape"]
+    rho = workloads.initial_densities(shape, w["seed"]).reshape(2, -1)
+    x, bonds = workloads.particles_for(w)
+    return w, shape, rho, x, bonds
+
+
+@pytest.mark.parametrize("name", ["c2_256", "c3"])
+def test_one_step_sampled_full_size(name):
+    import bench
+    import torch
+    print("full-size sampled parity: %s" % name, flush=True)
+    torch.cuda.set_device(0)
+    st = torch.cuda.Stream()
+    sim, w, npart = bench.setup(name, st.cuda_stream, lbmd.KERNEL_AUTO, None)
+    shape = w["shape"]
+    N = int(np.prod(shape))
+    rho = workloads.initial_densities(shape, w["seed"]).reshape(2, -1)
+    x0, bonds = workloads.particles_for(w)
+    sim.step(1)
+    assert sim.sync() == lbmd.OK, sim.last_error()
+    pop = torch.empty(38 * N, dtype=torch.float64, device="cuda")
+    sim.get_fields_device(lbmd.POP, pop.data_ptr())
+    torch.cuda.synchronize()
+    xg, vg, Fg, Fcg = sim.particles()
+
+    P = oracle.make_params(shape, tau=w["tau"], G=w["G"], gamma=w["gamma"], kT=w["kT"], seed=w["seed"],
+                           kappa=w["kappa"], mass=w["mass"], charge=w["charge"], wca=w["wca"], fene=w["fene"],
+                           dh=w["dh"])
+    f0 = oracle.init_populations(P, rho)
+    types = np.zeros(len(x0), np.int32)
+    v0 = np.zeros_like(x0)
+    # first half kick and drift with F(0) = 0, v(0) = 0: positions unchanged
+    g = np.random.default_rng(99)
+    # sampled sites: random ones and particle-touched nodes
+    touched = []
+    for p in g.choice(len(x0), 120, replace=False):
+        node, _ = oracle.interp_weights(x0[p], shape)
+        touched.append(int(node[g.integers(0, 8)]))
+    sites = np.concatenate([g.integers(0, N, 120), np.array(touched)])
+    c, _ = oracle.lattice()
+    nx, ny, nz = shape
+    idx = []
+    want = []
+    cache = {}
+    for s in sites:
+        x, y, z = s % nx, (s // nx) % ny, s // (nx * ny)
+        for i in range(19):
+            up = (((z - c[i, 2]) % nz) * ny + (y - c[i, 1]) % ny) * nx + (x - c[i, 0]) % nx
+            if up not in cache:
+                gP = oracle.particle_force_at(P, 0, f0, x0, v0, types, up)
+                cache[up] = oracle.site_collide(P, 0, f0, up, gP)
+            for comp in range(2):
+                idx.append((comp * 19 + i) * N + s)
+                want.append(cache[up][comp, i])
+    got = pop[torch.as_tensor(np.array(idx), device="cuda")].cpu().numpy()
+    want = np.array(want)
+    err = np.max(np.abs(got - want) / np.abs(want))
+    print("sampled populations: %d values, max rel err %.3e" % (len(want), err), flush=True)
+    assert err <= 1e-5
+    # sampled particles: coupling force, total force, velocity after the step.
+    # The solvation force is a lattice gradient of O(1) densities that differ
+    # by ~1 %, so FP32 storage enters it at ~eps * rho / c_s^2: the bound is
+    # relative to that input scale, 3 sum|kappa| rho_max, not to the force.
+    fscale = 3.0 * float(np.abs(np.asarray(w["kappa"][0])).sum()) * float(rho.max())
+    m = w["mass"][0]
+    for p in g.choice(len(x0), 60, replace=False):
+        Fc = oracle.coupling_force_one(P, 0, f0, x0[p], v0[p], 0, p)
+        stc, Fcons = oracle.conservative_force_one(P, x0, p, types, bonds)
+        assert stc == oracle.OK
+        F = Fc + Fcons
+        tol = 1e-5 * max(np.abs(F).max(), np.abs(Fc).max(), fscale)
+        assert np.abs(Fcg[p] - Fc).max() <= tol, (p, Fcg[p], Fc)
+        assert np.abs(Fg[p] - F).max() <= tol, (p, Fg[p], F)
+        assert np.abs(vg[p] - 0.5 * F / m).max() <= tol / m
+    # mass per component after 10 more steps (FP64 device sums of FP32 storage)
+    sim.step(1)
+    r0, _ = sim.reductions()
+    sim.step(10)
+    r1, _ = sim.reductions()
+    assert abs(r1[0] - r0[0]) / r0[0] < 1e-6 and abs(r1[1] - r0[1]) / r0[1] < 1e-6
+    sim.close()
+
+
+def test_instability_onset_matches_oracle():
+    """G_AB = 1.8, tau = 1, psi = rho: spinodal decomposition from the seeded
+    uniform mixture drives a density negative; the GPU latches the failure
+    at the same step as the oracle."""
+    shape = (32, 32, 32)
+    w = workloads.WORKLOADS["c2_256"]
+    rho = workloads.initial_densities(shape, w["seed"]).reshape(2, -1)
+    G = ((0.0, 1.8), (1.8, 0.0))
+    P = oracle.make_params(shape, G=G)
+    o = oracle.Sim(P, rho)
+    bad_o = None
+    for k in range(300):
+        if o.step(1) == oracle.EUNSTABLE:
+            bad_o = k
+            break
+    assert bad_o is not None and 80 < bad_o < 300
+    g = lbmd.Sim(shape, precision=lbmd.FP64, G=G, rho_init=rho)
+    g.step(bad_o + 5)
+    assert g.sync() == lbmd.EUNSTABLE
+    msg = g.last_error()
+    bad_g = int(msg.split("step ")[1].split()[0])
+    print("first unstable step: oracle %d, GPU %d" % (bad_o, bad_g), flush=True)
+    assert abs(bad_g - bad_o) <= 1
