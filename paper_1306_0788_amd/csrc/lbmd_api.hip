@@ -106,6 +106,7 @@ void free_particles(lbmd_ctx* h) {
   dfree(h->v);
   dfree(h->F);
   dfree(h->Fc);
+  dfree(h->Fcons);
   dfree(h->type);
   dfree(h->cell_of);
   dfree(h->rank_of);
@@ -229,6 +230,10 @@ int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, 
     if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) return bail(LBMD_EDEVICE);
     h->own_stream = true;
   }
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_sorted, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_pairs, hipEventDisableTiming) != hipSuccess)
+    return bail(LBMD_EDEVICE);
   const size_t pop = size_t(2) * 19 * h->N * h->s_bytes;
   for (int b = 0; b < 2; ++b)
     if (hipMalloc(&h->f[b], pop) != hipSuccess) return bail(LBMD_ENOMEM);
@@ -283,6 +288,10 @@ int lbmd_destroy(lbmd_handle h) {
   dfree(h->nflag);
   dfree(h->export_tmp);
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+  if (h->side) (void)hipStreamSynchronize(h->side);
+  if (h->ev_sorted) (void)hipEventDestroy(h->ev_sorted);
+  if (h->ev_pairs) (void)hipEventDestroy(h->ev_pairs);
+  if (h->side) (void)hipStreamDestroy(h->side);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return LBMD_OK;
@@ -318,6 +327,7 @@ int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double
     HIPCHECK(h, dalloc(&h->v, 3 * n));
     HIPCHECK(h, dalloc(&h->F, 3 * n));
     HIPCHECK(h, dalloc(&h->Fc, 3 * n));
+    HIPCHECK(h, dalloc(&h->Fcons, 3 * n));
     HIPCHECK(h, dalloc(&h->type, n));
     HIPCHECK(h, dalloc(&h->cell_of, n));
     HIPCHECK(h, dalloc(&h->rank_of, n));
@@ -447,8 +457,12 @@ int lbmd_step(lbmd_handle h, int64_t nsteps) {
   if (h->latched) return fail(h, LBMD_ESTATE, "step: a numerical failure is latched");
   for (int64_t k = 0; k < nsteps; ++k) {
     const bool parts = h->np > 0;
-    if (parts) HIPCHECK(h, particles_begin(h));
-    else h->red_part_used = 0;
+    if (parts) {
+      HIPCHECK(h, particles_begin(h));
+      HIPCHECK(h, particles_pairs(h));
+    } else {
+      h->red_part_used = 0;
+    }
     HIPCHECK(h, fluid_pass_a(h));
     if (parts) HIPCHECK(h, particles_forces(h));
     HIPCHECK(h, fluid_pass_b(h));

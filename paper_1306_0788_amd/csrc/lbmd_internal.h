@@ -118,6 +118,8 @@ struct lbmd_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t side = nullptr;  // second stream: pair forces next to the density pass
+  hipEvent_t ev_sorted = nullptr, ev_pairs = nullptr;
   size_t s_bytes = 8;  // bytes per stored population
 
   // fluid state: populations in the pull layout (buffer value at s for
@@ -142,6 +144,7 @@ struct lbmd_ctx {
   // particles (always float64)
   int64_t np = 0, np_cap = 0;
   double *x = nullptr, *v = nullptr, *F = nullptr, *Fc = nullptr;
+  double* Fcons = nullptr;  // conservative forces of the step being taken
   int32_t* type = nullptr;
   int32_t* cell_of = nullptr;  // pair-force cell of each particle
   int32_t* rank_of = nullptr;  // arrival rank inside its cell
@@ -192,6 +195,7 @@ hipError_t finalize_step(lbmd_ctx* h);  // reductions, counters
 int organisation_of(const lbmd_ctx* h);  // LBMD_KERNEL_FUSED or _TWOPASS this step
 // launchers (lbmd_particles.hip)
 hipError_t particles_begin(lbmd_ctx* h);  // reduction terms, half kick, drift, flags, cells
-hipError_t particles_forces(lbmd_ctx* h); // coupling + conservative forces, spread
+hipError_t particles_pairs(lbmd_ctx* h);  // conservative forces (side stream)
+hipError_t particles_forces(lbmd_ctx* h); // coupling forces, total force, spread
 hipError_t particles_end(lbmd_ctx* h);    // second half kick
 }  // namespace lbmd

@@ -211,46 +211,21 @@ __device__ __forceinline__ void add_radial(double fr, const double (&d)[3], doub
   for (int a = 0; a < 3; ++a) Fp[a] -= fr * d[a] / r;
 }
 
-template <class C>
-__global__ __launch_bounds__(256) void k_forces(PartArgs A, const double* __restrict__ x, const double* __restrict__ v,
-                                                double* __restrict__ F, double* __restrict__ Fc,
-                                                const int32_t* __restrict__ type, const C* __restrict__ rec,
-                                                C* __restrict__ gP, const int32_t* __restrict__ cell_start,
-                                                const int32_t* __restrict__ cell_count_unused,
-                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ cell_of,
-                                                const int32_t* __restrict__ bstart, const int32_t* __restrict__ bnbr,
-                                                uint32_t* status, long long* bad) {
+// Conservative forces (pair potentials from the cell list, FENE bonds) at
+// the new positions; independent of the fluid, so it runs on a second stream
+// while the density pass streams the populations.
+__global__ __launch_bounds__(256) void k_pairs(PartArgs A, const double* __restrict__ x,
+                                               const int32_t* __restrict__ type,
+                                               const int32_t* __restrict__ cell_start,
+                                               const int32_t* __restrict__ perm, const int32_t* __restrict__ cell_of,
+                                               const int32_t* __restrict__ bstart, const int32_t* __restrict__ bnbr,
+                                               double* __restrict__ Fcons) {
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (tid >= A.np) return;
-  // particles in cell order: neighbouring threads share cells and nodes
+  // particles in cell order: neighbouring threads share cells
   const int64_t p = A.use_cells ? int64_t(perm[tid]) : tid;
   const int t = type[p];
   const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
-  int64_t node[8];
-  double W[8];
-  interp(xp, A.nx, A.ny, A.nz, node, W);
-  // interpolated fluid velocity and lattice density gradients (grad = N/c_s^2)
-  double up[3] = {0, 0, 0}, gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int64_t s = node[k];
-    const C* r = rec + s * 16;
-    for (int a = 0; a < 3; ++a) {
-      gA[a] += W[k] * 3.0 * double(r[a]);
-      gB[a] += W[k] * 3.0 * double(r[3 + a]);
-      up[a] += W[k] * double(r[6 + a]);
-    }
-  }
-  double R[4] = {0, 0, 0, 0};
-  if (A.kT > 0.0) {
-    normals4<double>(A.seed, A.step, uint32_t(p), 0u, 1u, R);
-    const double amp = sqrt(2.0 * A.kT * A.gamma);
-    for (int a = 0; a < 3; ++a) R[a] *= amp;
-  }
-  double fc[3];
-  for (int a = 0; a < 3; ++a)
-    fc[a] = -A.gamma * (v[3 * p + a] - up[a]) - (A.T.kappa[t][0] * gA[a] + A.T.kappa[t][1] * gB[a]) + R[a];
-  // conservative forces
   double Fp[3] = {0, 0, 0};
   const double L[3] = {double(A.nx), double(A.ny), double(A.nz)};
   if (A.use_cells) {
@@ -271,23 +246,23 @@ __global__ __launch_bounds__(256) void k_forces(PartArgs A, const double* __rest
           ++nr;
         }
     for (int rr = 0; rr < nr; ++rr) {
-          for (int jj = rb[rr]; jj < re[rr]; ++jj) {
-            const int q = perm[jj];
-            if (q == p) continue;
-            double d[3];
-            for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
-            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            const double r = sqrt(r2);
-            if (A.pp.wca_on && r2 < A.pp.wca_rc2) {
-              const double s2 = A.pp.wca_sigma * A.pp.wca_sigma / r2;
-              const double s6 = s2 * s2 * s2;
-              add_radial(24.0 * A.pp.wca_eps * (2.0 * s6 * s6 - s6) / r, d, r, Fp);
-            }
-            if (A.pp.dh_on && r < A.pp.dh_rc) {
-              const double qq = qp * A.T.charge[type[q]];
-              add_radial(qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) / r2, d, r, Fp);
-            }
-          }
+      for (int jj = rb[rr]; jj < re[rr]; ++jj) {
+        const int q = perm[jj];
+        if (q == p) continue;
+        double d[3];
+        for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const double r = sqrt(r2);
+        if (A.pp.wca_on && r2 < A.pp.wca_rc2) {
+          const double s2 = A.pp.wca_sigma * A.pp.wca_sigma / r2;
+          const double s6 = s2 * s2 * s2;
+          add_radial(24.0 * A.pp.wca_eps * (2.0 * s6 * s6 - s6) / r, d, r, Fp);
+        }
+        if (A.pp.dh_on && r < A.pp.dh_rc) {
+          const double qq = qp * A.T.charge[type[q]];
+          add_radial(qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) / r2, d, r, Fp);
+        }
+      }
     }
   }
   if (A.pp.fene_on && bstart) {
@@ -301,10 +276,50 @@ __global__ __launch_bounds__(256) void k_forces(PartArgs A, const double* __rest
       add_radial(fr, d, r, Fp);
     }
   }
+  for (int a = 0; a < 3; ++a) Fcons[3 * p + a] = Fp[a];
+}
+
+// Coupling force: trilinear interpolation of u_c and the lattice density
+// gradients (N / c_s^2) from the node records, friction + solvation (Eq.
+// solvation_kappa) + random force; total force F = coupling + conservative;
+// the opposite coupling force spread onto the 8 nodes.
+template <class C>
+__global__ __launch_bounds__(256) void k_couple(PartArgs A, const double* __restrict__ x,
+                                                const double* __restrict__ v, double* __restrict__ F,
+                                                double* __restrict__ Fc, const double* __restrict__ Fcons,
+                                                const int32_t* __restrict__ type, const C* __restrict__ rec,
+                                                C* __restrict__ gP, const int32_t* __restrict__ perm,
+                                                uint32_t* status, long long* bad) {
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= A.np) return;
+  const int64_t p = A.use_cells ? int64_t(perm[tid]) : tid;
+  const int t = type[p];
+  const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
+  int64_t node[8];
+  double W[8];
+  interp(xp, A.nx, A.ny, A.nz, node, W);
+  double up[3] = {0, 0, 0}, gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const C* r = rec + node[k] * 16;
+    for (int a = 0; a < 3; ++a) {
+      gA[a] += W[k] * 3.0 * double(r[a]);
+      gB[a] += W[k] * 3.0 * double(r[3 + a]);
+      up[a] += W[k] * double(r[6 + a]);
+    }
+  }
+  double R[4] = {0, 0, 0, 0};
+  if (A.kT > 0.0) {
+    normals4<double>(A.seed, A.step, uint32_t(p), 0u, 1u, R);
+    const double amp = sqrt(2.0 * A.kT * A.gamma);
+    for (int a = 0; a < 3; ++a) R[a] *= amp;
+  }
+  double fc[3];
   bool ok = true;
   for (int a = 0; a < 3; ++a) {
+    fc[a] = -A.gamma * (v[3 * p + a] - up[a]) - (A.T.kappa[t][0] * gA[a] + A.T.kappa[t][1] * gB[a]) + R[a];
     Fc[3 * p + a] = fc[a];
-    const double Ft = fc[a] + Fp[a];
+    const double Ft = fc[a] + (Fcons ? Fcons[3 * p + a] : 0.0);
     F[3 * p + a] = Ft;
     ok = ok && isfinite(Ft);
   }
@@ -369,17 +384,36 @@ hipError_t particles_begin(lbmd_ctx* h) {
   return hipGetLastError();
 }
 
+bool has_conservative(const lbmd_ctx* h) {
+  return h->pair.wca_on || h->pair.dh_on || (h->pair.fene_on && h->bond_start);
+}
+
+// conservative forces on the side stream, ordered after the kick/drift/cell
+// sort on the main stream; the main stream waits for them before coupling
+hipError_t particles_pairs(lbmd_ctx* h) {
+  if (!has_conservative(h)) return hipSuccess;
+  PartArgs A = args(h);
+  if (hipError_t e = hipEventRecord(h->ev_sorted, h->stream)) return e;
+  if (hipError_t e = hipStreamWaitEvent(h->side, h->ev_sorted, 0)) return e;
+  hipLaunchKernelGGL(k_pairs, dim3((h->np + 255) / 256), dim3(256), 0, h->side, A, h->x, h->type, h->cell_start,
+                     h->cell_perm, h->cell_of, h->bond_start, h->bond_nbr, h->Fcons);
+  if (hipError_t e = hipGetLastError()) return e;
+  return hipEventRecord(h->ev_pairs, h->side);
+}
+
 hipError_t particles_forces(lbmd_ctx* h) {
   PartArgs A = args(h);
+  const bool cons = has_conservative(h);
+  if (cons)
+    if (hipError_t e = hipStreamWaitEvent(h->stream, h->ev_pairs, 0)) return e;
   const int64_t nb = (h->np + 255) / 256;
+  const double* Fcons = cons ? h->Fcons : nullptr;
   if (h->p.precision == LBMD_FP64)
-    hipLaunchKernelGGL(k_forces<double>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, h->type,
-                       (const double*)h->rec, (double*)h->gP, h->cell_start, h->cell_count, h->cell_perm, h->cell_of,
-                       h->bond_start, h->bond_nbr, h->status, h->bad_step);
+    hipLaunchKernelGGL(k_couple<double>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, Fcons,
+                       h->type, (const double*)h->rec, (double*)h->gP, h->cell_perm, h->status, h->bad_step);
   else
-    hipLaunchKernelGGL(k_forces<float>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, h->type,
-                       (const float*)h->rec, (float*)h->gP, h->cell_start, h->cell_count, h->cell_perm, h->cell_of,
-                       h->bond_start, h->bond_nbr, h->status, h->bad_step);
+    hipLaunchKernelGGL(k_couple<float>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, Fcons,
+                       h->type, (const float*)h->rec, (float*)h->gP, h->cell_perm, h->status, h->bad_step);
   return hipGetLastError();
 }
 
