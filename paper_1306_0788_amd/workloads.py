@@ -25,33 +25,38 @@ import numpy as np
 WCA_CUT = 2.0 ** (1.0 / 6.0)
 
 # Parameter sets.  "shape" = (nx, ny, nz); G is the 2x2 coupling matrix.
+# "onset" is the first step at which a density reaches zero when the set-up
+# starts from its seeded uniform mixture (G_AB = 1.8 is 1.8 times the spinodal
+# coupling of the rho = 1 mixture; the decomposition overshoots the
+# coexistence densities and drains the minority component), as measured for
+# these seeds; None where the run length stays below it.
 WORKLOADS = {
     # 32^3 FP64, velocity-shift forcing, 64 free particles, friction only.
     "c1": dict(shape=(32, 32, 32), precision="fp64", forcing="shift", tau=(1.0, 1.0),
                G=((0.0, 1.6), (1.6, 0.0)), gamma=0.5, kT=0.0, seed=1,
                kappa=((0.0, 0.0),), mass=(1.0,), charge=(0.0,),
                particles=dict(kind="free", n=64, min_dist=0.0), wca=None, fene=None, dh=None,
-               steps=100),
+               steps=100, onset=None),
     # 128^3 FP32 spinodal decomposition with 20,000 solvated WCA particles.
     "c2": dict(shape=(128, 128, 128), precision="fp32", forcing="paper", tau=(1.0, 1.0),
                G=((0.0, 1.8), (1.8, 0.0)), gamma=1.0, kT=0.0, seed=2,
                kappa=((0.05, 0.0),), mass=(100.0,), charge=(0.0,),
                particles=dict(kind="free", n=20000, min_dist=WCA_CUT), wca=(1.0, 1.0), fene=None,
-               dh=None, steps=2000),
+               dh=None, steps=2000, onset=117),
     # 256^3 FP32 polyelectrolyte-like mixture: 2,000 chains x 100 beads,
     # FENE + WCA + screened Debye-Hueckel, fluctuating fluid.
     "c3": dict(shape=(256, 256, 256), precision="fp32", forcing="paper", tau=(1.0, 1.0),
                G=((0.0, 1.8), (1.8, 0.0)), gamma=1.0, kT=1e-4, seed=3,
                kappa=((0.1, 0.0),), mass=(2000.0,), charge=(1.0,),
-               particles=dict(kind="chains", nchains=2000, nbeads=100, bond=0.97, min_dist=0.9),
-               wca=(1.0, 1.0), fene=(30.0, 1.5), dh=(1.0, 3.0, 1.0), steps=1000),
+               particles=dict(kind="chains", nchains=2000, nbeads=100, bond=0.97, min_dist=WCA_CUT),
+               wca=(1.0, 1.0), fene=(30.0, 1.5), dh=(1.0, 3.0, 1.0), steps=1000, onset=87),
     # The 128^3 spinodal set-up at 256^3 (same particle number density:
     # 160,000 particles), plain FP32 storage.
     "c2_256": dict(shape=(256, 256, 256), precision="fp32", forcing="paper", tau=(1.0, 1.0),
                    G=((0.0, 1.8), (1.8, 0.0)), gamma=1.0, kT=0.0, seed=6,
                    kappa=((0.05, 0.0),), mass=(100.0,), charge=(0.0,),
                    particles=dict(kind="free", n=160000, min_dist=WCA_CUT), wca=(1.0, 1.0),
-                   fene=None, dh=None, steps=200),
+                   fene=None, dh=None, steps=200, onset=117),
 }
 
 
@@ -122,7 +127,7 @@ def free_particles(n, shape, seed, min_dist=0.0, max_tries=1000):
     return pts
 
 
-def chains(nchains, nbeads, shape, seed, bond=0.97, min_dist=0.9, max_tries=200, max_restarts=100):
+def chains(nchains, nbeads, shape, seed, bond=0.97, min_dist=WCA_CUT, max_tries=200, max_restarts=100):
     """Random-walk chains.  Returns positions [nchains*nbeads][3] (wrapped into
     the box) and bonds [nchains*(nbeads-1)][2] (int32).  A chain whose next
     bead cannot be placed is removed and started again elsewhere, so no two

@@ -35,7 +35,7 @@ class Case:
         if positions is not None:
             self.x = np.asarray(positions, dtype=float).reshape(-1, 3)
         elif chains is not None:
-            self.x, self.bonds = workloads.chains(chains[0], chains[1], self.shape, seed, bond=0.97, min_dist=0.9)
+            self.x, self.bonds = workloads.chains(chains[0], chains[1], self.shape, seed, bond=0.97, min_dist=workloads.WCA_CUT)
         else:
             self.x = workloads.free_particles(npart, self.shape, seed, min_dist)
         n = len(self.x)

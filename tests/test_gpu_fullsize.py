@@ -125,3 +125,25 @@ def test_instability_onset_matches_oracle():
     bad_g = int(msg.split("step ")[1].split()[0])
     print("first unstable step: oracle %d, GPU %d" % (bad_o, bad_g), flush=True)
     assert abs(bad_g - bad_o) <= 1
+
+
+@pytest.mark.parametrize("name", ["c2", "c2_256", "c3"])
+def test_recorded_onset(name):
+    """The step at which each G_AB = 1.8 workload first drives a density to
+    zero, in the bench configuration, is the one recorded with the workload
+    (the bench keeps its timed window below it)."""
+    import bench
+    import torch
+    torch.cuda.set_device(0)
+    st = torch.cuda.Stream()
+    sim, w, _ = bench.setup(name, st.cuda_stream, lbmd.KERNEL_AUTO, None)
+    onset = w["onset"]
+    print("onset check: %s, recorded %d" % (name, onset), flush=True)
+    sim.step(onset - 3)
+    assert sim.sync() == lbmd.OK, sim.last_error()
+    sim.step(6)
+    assert sim.sync() == lbmd.EUNSTABLE
+    bad = int(sim.last_error().split("step ")[1].split()[0])
+    print("first unstable step %d" % bad, flush=True)
+    assert abs(bad - onset) <= 2
+    sim.close()
