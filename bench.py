@@ -54,13 +54,19 @@ def measured_traffic(kernel_name, workload):
     return float(t.group(1))
 
 
-def setup(workload, stream, kernel, tiling):
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3}
+STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp16dev": 2, "bf16dev": 2}
+
+
+def setup(workload, stream, kernel, tiling, precision=None):
+    """The workload's simulation on the given stream; precision (a key of
+    PRECISIONS) replaces the workload's storage precision if given."""
     from paper_1306_0788_amd import lbmd, workloads
     w = workloads.WORKLOADS[workload]
     shape = w["shape"]
     rho = workloads.initial_densities(shape, w["seed"]).reshape(2, -1)
     x, bonds = workloads.particles_for(w)
-    prec = lbmd.FP32 if w["precision"] == "fp32" else lbmd.FP64
+    prec = PRECISIONS[precision or w["precision"]]
     forcing = lbmd.FORCE_SHIFT if w["forcing"] == "shift" else lbmd.FORCE_PAPER
     sim = lbmd.Sim(shape, precision=prec, forcing=forcing, kernel=kernel, tau=w["tau"], G=w["G"],
                    gamma=w["gamma"], kappa=w["kappa"][0], mass=w["mass"][0], kT=w["kT"], seed=w["seed"],
@@ -140,6 +146,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2_256")
     ap.add_argument("--kernel", choices=["auto", "fused", "twopass"], default="auto")
+    ap.add_argument("--precision", choices=sorted(PRECISIONS), default=None,
+                    help="population storage (default: the workload's); fp16dev / bf16dev store f - w rho0")
     ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("TILE_Y", "TILE_Z"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -172,10 +180,12 @@ def main():
     torch.cuda.set_stream(stream)
     kernel = {"auto": lbmd.KERNEL_AUTO, "fused": lbmd.KERNEL_FUSED, "twopass": lbmd.KERNEL_TWOPASS}[args.kernel]
     print("bench: setting up %s" % args.workload, file=sys.stderr, flush=True)
-    sim, w, npart = setup(args.workload, stream.cuda_stream, kernel, args.tiling)
+    sim, w, npart = setup(args.workload, stream.cuda_stream, kernel, args.tiling, args.precision)
     sim_org = sim.organisation()
     N = int(np.prod(w["shape"]))
-    s_bytes = 4 if w["precision"] == "fp32" else 8
+    prec_name = args.precision or w["precision"]
+    s_bytes = STORAGE_BYTES[prec_name]
+    label = args.workload if prec_name == w["precision"] else "%s_%s" % (args.workload, prec_name)
 
     print("bench: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
     sim.step(args.warmup)
@@ -203,7 +213,7 @@ def main():
     kavg_s = kms * 1e-3 / max(launches, 1)
     achieved = alg_bytes / kavg_s / 1e9
     kname = "k_fused" if sim_org == lbmd.KERNEL_FUSED else "k_collide"
-    traffic = measured_traffic(kname, args.workload)
+    traffic = measured_traffic(kname, label)
     line = {
         "metric": "MLUPS (2-component D3Q19 Shan-Chen + coupled particles, one full step)",
         "value": round(mlups, 2),
@@ -215,9 +225,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if s_bytes == 4 else "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16 storage, f32 math",
+                  "bf16dev": "bf16 storage, f32 math"}[prec_name],
         "data": "synthetic",
-        "config": {"workload": args.workload, "lattice": list(w["shape"]), "particles": npart,
+        "config": {"workload": label, "lattice": list(w["shape"]), "particles": npart,
+                   "storage": prec_name,
                    "forcing": w["forcing"], "kT": w["kT"],
                    "kernel": "fused" if sim_org == lbmd.KERNEL_FUSED else "twopass",
                    "particle_updates_per_s": round(npart * args.steps / (ms * 1e-3), 1)},

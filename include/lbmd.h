@@ -64,9 +64,17 @@ typedef struct lbmd_ctx* lbmd_handle;
 #define LBMD_EUNSTABLE (-4) /* numerical failure latched on the device  */
 #define LBMD_ESTATE (-5)    /* call not valid in the handle's state     */
 
-/* storage precision of the populations (arithmetic is done in the same type) */
+/* storage precision of the populations.  FP64 and FP32 store f and compute
+   in the same type.  FP16DEV and BF16DEV store the deviation f_i - w_i rho0
+   from the rest equilibrium of density rho0 (same rho0 for both components)
+   as IEEE binary16 or bfloat16 and do all arithmetic, the density field and
+   the particle coupling in FP32; rounding the stored deviation is not
+   mass-conserving (the drift is visible in lbmd_reductions).  Global sums
+   are FP64 in every mode. */
 #define LBMD_FP64 0
 #define LBMD_FP32 1
+#define LBMD_FP16DEV 2
+#define LBMD_BF16DEV 3
 
 /* forcing scheme */
 #define LBMD_FORCE_PAPER 0 /* Appendix forcing source term with the half-force
@@ -102,7 +110,7 @@ typedef struct lbmd_ctx* lbmd_handle;
 
 typedef struct {
   int32_t nx, ny, nz;  /* periodic lattice, each >= 1                       */
-  int32_t precision;   /* LBMD_FP64 or LBMD_FP32                            */
+  int32_t precision;   /* LBMD_FP64, _FP32, _FP16DEV or _BF16DEV            */
   int32_t forcing;     /* LBMD_FORCE_PAPER or LBMD_FORCE_SHIFT              */
   int32_t kernel;      /* LBMD_KERNEL_FUSED, _TWOPASS or _AUTO              */
   double tau[2];       /* BGK relaxation time per component, > 1/2          */
@@ -118,6 +126,8 @@ typedef struct {
   int32_t check_every; /* lbmd_step polls the status word every this many
                           steps (0 = never; errors surface at sync/get)     */
   int32_t reserved;    /* must be 0                                         */
+  double rho0;         /* reference density of the deviation storage (> 0,
+                          finite) for FP16DEV / BF16DEV; ignored otherwise  */
 } lbmd_params;
 
 /* Create a simulation.  rho_init: host [2][N] initial densities, or NULL for

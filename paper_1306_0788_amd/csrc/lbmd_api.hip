@@ -53,6 +53,11 @@ bool finite_all(const double* a, size_t n) {
   return true;
 }
 
+// bytes per stored population
+static size_t storage_bytes(int precision) {
+  return precision == LBMD_FP64 ? 8 : (precision == LBMD_FP32 ? 4 : 2);
+}
+
 int validate(const lbmd_params* p, std::string& why) {
   if (!p) return why = "params is NULL", LBMD_EINVAL;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return why = "lattice size must be >= 1", LBMD_EINVAL;
@@ -60,9 +65,13 @@ int validate(const lbmd_params* p, std::string& why) {
   if (n > 2147483647.0) return why = "lattice has more than 2^31-1 sites", LBMD_EINVAL;
   // kernels address the 19 arrays of a component through one buffer
   // resource (32-bit byte range)
-  if (19.0 * n * (p->precision == LBMD_FP64 ? 8.0 : 4.0) >= 4294967296.0)
+  if (p->precision != LBMD_FP64 && p->precision != LBMD_FP32 && p->precision != LBMD_FP16DEV &&
+      p->precision != LBMD_BF16DEV)
+    return why = "unknown precision", LBMD_EINVAL;
+  if (19.0 * n * double(storage_bytes(p->precision)) >= 4294967296.0)
     return why = "the 19 population arrays of a component must stay below 4 GiB", LBMD_EINVAL;
-  if (p->precision != LBMD_FP64 && p->precision != LBMD_FP32) return why = "unknown precision", LBMD_EINVAL;
+  if ((p->precision == LBMD_FP16DEV || p->precision == LBMD_BF16DEV) && !(p->rho0 > 0 && std::isfinite(p->rho0)))
+    return why = "deviation storage needs a finite rho0 > 0", LBMD_EINVAL;
   if (p->forcing != LBMD_FORCE_PAPER && p->forcing != LBMD_FORCE_SHIFT) return why = "unknown forcing", LBMD_EINVAL;
   if (p->kernel != LBMD_KERNEL_FUSED && p->kernel != LBMD_KERNEL_TWOPASS && p->kernel != LBMD_KERNEL_AUTO)
     return why = "unknown kernel", LBMD_EINVAL;
@@ -157,10 +166,10 @@ int ensure_coupling_buffers(lbmd_ctx* h) {
   const size_t words = (h->N + 31) / 32;
   HIPCHECK(h, dalloc(&h->mask, words));
   HIPCHECK(h, hipMemsetAsync(h->mask, 0, words * sizeof(uint32_t), h->stream));
-  HIPCHECK(h, hipMalloc(&h->rec, 16 * h->N * h->s_bytes));
-  HIPCHECK(h, hipMalloc(&h->gP, 4 * h->N * h->s_bytes));
-  HIPCHECK(h, hipMemsetAsync(h->gP, 0, 4 * h->N * h->s_bytes, h->stream));
-  HIPCHECK(h, hipMemsetAsync(h->rec, 0, 16 * h->N * h->s_bytes, h->stream));
+  HIPCHECK(h, hipMalloc(&h->rec, 16 * h->N * h->c_bytes));
+  HIPCHECK(h, hipMalloc(&h->gP, 4 * h->N * h->c_bytes));
+  HIPCHECK(h, hipMemsetAsync(h->gP, 0, 4 * h->N * h->c_bytes, h->stream));
+  HIPCHECK(h, hipMemsetAsync(h->rec, 0, 16 * h->N * h->c_bytes, h->stream));
   return LBMD_OK;
 }
 
@@ -210,7 +219,8 @@ int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, 
   if (!h) return LBMD_ENOMEM;
   h->p = *p;
   h->N = int64_t(p->nx) * p->ny * p->nz;
-  h->s_bytes = p->precision == LBMD_FP64 ? 8 : 4;
+  h->s_bytes = storage_bytes(p->precision);
+  h->c_bytes = p->precision == LBMD_FP64 ? 8 : 4;
   h->types.ntypes = 1;
   for (int t = 0; t < LBMD_MAX_TYPES; ++t) {
     h->types.kappa[t][0] = p->kappa[0];
@@ -237,7 +247,7 @@ int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, 
   const size_t pop = size_t(2) * 19 * h->N * h->s_bytes;
   for (int b = 0; b < 2; ++b)
     if (hipMalloc(&h->f[b], pop) != hipSuccess) return bail(LBMD_ENOMEM);
-  if (hipMalloc(&h->rho, 2 * h->N * h->s_bytes) != hipSuccess) return bail(LBMD_ENOMEM);
+  if (hipMalloc(&h->rho, 2 * h->N * h->c_bytes) != hipSuccess) return bail(LBMD_ENOMEM);
   // reduction partials: the largest launch is the two-row fused tiling with
   // one plane per block, or the two-pass collide grid
   const int64_t tiles_x = (p->nx + 63) / 64;

@@ -43,10 +43,12 @@ template <class S>
 struct Pops {
   __amdgpu_buffer_rsrc_t r[2];
   uint32_t pstride;  // N * sizeof(S)
+  arith_t<S> rho0;   // deviation storage: w_i rho0 is added on load, removed on store
 };
 template <class S>
-__device__ __forceinline__ Pops<S> make_pops(const S* base, int64_t N) {
+__device__ __forceinline__ Pops<S> make_pops(const S* base, int64_t N, arith_t<S> rho0 = 0) {
   Pops<S> p;
+  p.rho0 = rho0;
   const uint32_t bytes = uint32_t(19 * N * int64_t(sizeof(S)));
 #pragma unroll
   for (int c = 0; c < 2; ++c)
@@ -61,6 +63,19 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, ui
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, double*) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(vo), int(so), 0));
 }
+template <bool IEEE>
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, dev16<IEEE>*) {
+  return dev_decode(__builtin_amdgcn_raw_buffer_load_b16(r, int(vo), int(so), 0), (dev16<IEEE>*)nullptr);
+}
+// population i of component c at byte offset vo, as the arithmetic type
+template <class S>
+__device__ __forceinline__ arith_t<S> load_pop(const Pops<S>& p, int c, uint32_t vo, int i) {
+  const arith_t<S> v = bload(p.r[c], vo, uint32_t(i) * p.pstride, (S*)nullptr);
+  if constexpr (Storage<S>::deviation)
+    return v + weight<arith_t<S>>(i) * p.rho0;
+  else
+    return v;
+}
 // AUX = 2: non-temporal store hint (the new populations are not read again
 // by this step); AUX = 0: plain store
 template <int AUX>
@@ -71,6 +86,17 @@ template <int AUX>
 __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r,
                                         int(vo), int(so), AUX);
+}
+
+// store population i of component c at byte offset vo (AUX as above)
+template <int AUX, class S>
+__device__ __forceinline__ void put_pop(const Pops<S>& p, int c, uint32_t vo, int i, arith_t<S> v) {
+  if constexpr (Storage<S>::deviation) {
+    const uint16_t b = dev_encode(v - weight<float>(i) * p.rho0, (S*)nullptr);
+    __builtin_amdgcn_raw_buffer_store_b16(b, p.r[c], int(vo), int(uint32_t(i) * p.pstride), AUX);
+  } else {
+    bstore<AUX>(S(v), p.r[c], vo, uint32_t(i) * p.pstride);
+  }
 }
 
 // pulled populations of site (x,y,z): f_i(s) = src[i][s - c_i]
@@ -88,7 +114,7 @@ __device__ __forceinline__ void pull(const Pops<S>& src, int x, int y, int z, in
     const uint32_t sz = D3Q19::cz[i] > 0 ? zm : (D3Q19::cz[i] < 0 ? zp : z0);
     const uint32_t vo = (sz + sy + sx) * uint32_t(sizeof(S));
 #pragma unroll
-    for (int c = 0; c < 2; ++c) f[c][i] = C(bload(src.r[c], vo, uint32_t(i) * src.pstride, (S*)nullptr));
+    for (int c = 0; c < 2; ++c) f[c][i] = C(load_pop(src, c, vo, i));
   }
 }
 
@@ -99,12 +125,12 @@ __device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int i = 0; i < 19; ++i) bstore<2>(S(f[c][i]), dst.r[c], vo, uint32_t(i) * dst.pstride);
+      for (int i = 0; i < 19; ++i) put_pop<2>(dst, c, vo, i, arith_t<S>(f[c][i]));
   } else {
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int i = 0; i < 19; ++i) bstore<0>(S(f[c][i]), dst.r[c], vo, uint32_t(i) * dst.pstride);
+      for (int i = 0; i < 19; ++i) put_pop<0>(dst, c, vo, i, arith_t<S>(f[c][i]));
   }
 }
 
@@ -145,8 +171,18 @@ __device__ __forceinline__ void block_sum5(double (&v)[5], double* out) {
 }
 
 // ------------------------------------------------------------ init / io
+// host-side value v of population i in storage form (deviations are taken
+// in double and rounded once)
 template <class S>
-__global__ void k_init(S* __restrict__ f, const double* __restrict__ rho, int nx, int ny, int nz) {
+__device__ __forceinline__ S encode_pop(double v, int i, double rho0) {
+  if constexpr (Storage<S>::deviation)
+    return S{dev_encode(float(v - weight<double>(i) * rho0), (S*)nullptr)};
+  else
+    return S(v);
+}
+
+template <class S>
+__global__ void k_init(S* __restrict__ f, const double* __restrict__ rho, int nx, int ny, int nz, double rho0) {
   const int64_t N = int64_t(nx) * ny * nz;
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= N) return;
@@ -156,12 +192,12 @@ __global__ void k_init(S* __restrict__ f, const double* __restrict__ rho, int nx
     const int64_t t = (int64_t(wrapi(z + D3Q19::cz[i], nz)) * ny + wrapi(y + D3Q19::cy[i], ny)) * nx +
                       wrapi(x + D3Q19::cx[i], nx);
     for (int c = 0; c < 2; ++c)
-      f[(int64_t(c) * 19 + i) * N + s] = S(weight<double>(i) * (rho ? rho[c * N + t] : 1.0));
+      f[(int64_t(c) * 19 + i) * N + s] = encode_pop<S>(weight<double>(i) * (rho ? rho[c * N + t] : 1.0), i, rho0);
   }
 }
 
 template <class S>
-__global__ void k_import(S* __restrict__ f, const double* __restrict__ pop, int nx, int ny, int nz) {
+__global__ void k_import(S* __restrict__ f, const double* __restrict__ pop, int nx, int ny, int nz, double rho0) {
   const int64_t N = int64_t(nx) * ny * nz;
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= N) return;
@@ -170,24 +206,27 @@ __global__ void k_import(S* __restrict__ f, const double* __restrict__ pop, int 
   for (int i = 0; i < 19; ++i) {
     const int64_t t = (int64_t(wrapi(z + D3Q19::cz[i], nz)) * ny + wrapi(y + D3Q19::cy[i], ny)) * nx +
                       wrapi(x + D3Q19::cx[i], nx);
-    for (int c = 0; c < 2; ++c) f[(int64_t(c) * 19 + i) * N + s] = S(pop[(int64_t(c) * 19 + i) * N + t]);
+    for (int c = 0; c < 2; ++c)
+      f[(int64_t(c) * 19 + i) * N + s] = encode_pop<S>(pop[(int64_t(c) * 19 + i) * N + t], i, rho0);
   }
 }
 
 // density field rho[2][N] (two-pass kernel and exports)
 template <class S>
-__global__ void k_density(const S* __restrict__ src, S* __restrict__ rho, int nx, int ny, int nz) {
+__global__ void k_density(const S* __restrict__ src, arith_t<S>* __restrict__ rho, int nx, int ny, int nz,
+                          arith_t<S> rho0) {
+  using C = arith_t<S>;
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int z = blockIdx.z;
   if (x >= nx || y >= ny) return;
   const int64_t N = int64_t(nx) * ny * nz;
-  S f[2][19];
-  pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
+  C f[2][19];
+  pull<S, C>(make_pops(src, N, rho0), x, y, z, nx, ny, nz, f);
   const int64_t s = (int64_t(z) * ny + y) * nx + x;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    S r = f[c][0];
+    C r = f[c][0];
 #pragma unroll
     for (int i = 1; i < 19; ++i) r += f[c][i];
     rho[c * N + s] = r;
@@ -254,8 +293,9 @@ __device__ __forceinline__ SiteOut<C> moments_only(const C (&f)[2][19]) {
 
 // export: rho [2][N], u_c [3][N], populations [2][19][N] as float64
 template <class S>
-__global__ void k_export(const S* __restrict__ src, const S* __restrict__ rho, double* __restrict__ out,
-                         FluidConsts<S> K, uint32_t mask) {
+__global__ void k_export(const S* __restrict__ src, const arith_t<S>* __restrict__ rho, double* __restrict__ out,
+                         FluidConsts<arith_t<S>> K, uint32_t mask) {
+  using C = arith_t<S>;
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int z = blockIdx.z;
@@ -263,8 +303,8 @@ __global__ void k_export(const S* __restrict__ src, const S* __restrict__ rho, d
   if (x >= nx || y >= ny) return;
   const int64_t N = K.N;
   const int64_t s = (int64_t(z) * ny + y) * nx + x;
-  S f[2][19];
-  pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
+  C f[2][19];
+  pull<S, C>(make_pops(src, N, K.rho0), x, y, z, nx, ny, nz, f);
   double* o = out;
   if (mask & LBMD_RHO) {
     o[s] = double(rho[s]);
@@ -272,10 +312,10 @@ __global__ void k_export(const S* __restrict__ src, const S* __restrict__ rho, d
     o += 2 * N;
   }
   if (mask & LBMD_U) {
-    S NA[3], NB[3], uc[3];
-    nsum_field<S, S>(rho, x, y, z, nx, ny, nz, N, NA, NB);
-    SiteOut<S> m = moments_only<S>(f);
-    velocity_uc<S>(m, NA, NB, K, uc);
+    C NA[3], NB[3], uc[3];
+    nsum_field<C, C>(rho, x, y, z, nx, ny, nz, N, NA, NB);
+    SiteOut<C> m = moments_only<C>(f);
+    velocity_uc<C>(m, NA, NB, K, uc);
     for (int a = 0; a < 3; ++a) o[a * N + s] = double(uc[a]);
     o += 3 * N;
   }
@@ -401,16 +441,16 @@ __device__ __forceinline__ void nsum_ring(const C (&ring)[4][2][TY + 2][66], int
 // every site without particle force, records at touched nodes; k_fix then
 // re-collides the touched nodes.  Best when few nodes are touched.
 template <class S, int TY, int FORCING, bool NOISE, bool HOLD>
-__global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S* __restrict__ dst_, FluidConsts<S> K,
-                                                    int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
-                                                    S* __restrict__ rec, double* __restrict__ red, uint32_t* status,
-                                                    long long* bad) {
-  using C = S;
+__global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S* __restrict__ dst_,
+                                                    FluidConsts<arith_t<S>> K, int tz, int tiles_x, int xcd,
+                                                    const uint32_t* __restrict__ mask, arith_t<S>* __restrict__ rec,
+                                                    double* __restrict__ red, uint32_t* status, long long* bad) {
+  using C = arith_t<S>;
   __shared__ C ring[4][2][TY + 2][66];
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
   const int64_t plane = int64_t(nx) * ny;
-  const Pops<S> src = make_pops(src_, N), dst = make_pops<S>(dst_, N);
+  const Pops<S> src = make_pops(src_, N, K.rho0), dst = make_pops<S>(dst_, N, K.rho0);
   const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
   const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
 
@@ -514,42 +554,44 @@ __global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S
 // re-collide the touched nodes with the spread particle force; clears the
 // node force and the mask as it goes
 template <class S, int FORCING, bool NOISE>
-__global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __restrict__ dst, FluidConsts<S> K,
-                                             const int32_t* __restrict__ list, const int32_t* __restrict__ nlist,
-                                             const S* __restrict__ rec, S* __restrict__ gP, uint32_t* __restrict__ mask) {
+__global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __restrict__ dst,
+                                             FluidConsts<arith_t<S>> K, const int32_t* __restrict__ list,
+                                             const int32_t* __restrict__ nlist, const arith_t<S>* __restrict__ rec,
+                                             arith_t<S>* __restrict__ gP, uint32_t* __restrict__ mask) {
+  using C = arith_t<S>;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= *nlist) return;
   const int64_t N = K.N;
   const int64_t s = list[t];
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int x = int(s % nx), y = int((s / nx) % ny), z = int(s / (int64_t(nx) * ny));
-  S f[2][19], NA[3], NB[3], gp[3];
-  pull<S, S>(make_pops(src, N), x, y, z, nx, ny, nz, f);
+  C f[2][19], NA[3], NB[3], gp[3];
+  pull<S, C>(make_pops(src, N, K.rho0), x, y, z, nx, ny, nz, f);
   for (int a = 0; a < 3; ++a) {
     NA[a] = rec[s * REC + a];
     NB[a] = rec[s * REC + 3 + a];
     gp[a] = gP[s * GPS + a];
-    gP[s * GPS + a] = S(0);
+    gP[s * GPS + a] = C(0);
   }
   mask[s >> 5] = 0u;
-  collide<S, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s));
-  store<S, S>(make_pops<S>(dst, N), uint32_t(s), f);
+  collide<C, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s));
+  store<S, C>(make_pops<S>(dst, N, K.rho0), uint32_t(s), f);
 }
 
 // ------------------------------------------------------------ split path
 // Pass P: density field, conservation sums, status, and the records at the
 // touched nodes (neighbour sums from the density ring, u_c).  No collision.
 template <class S, int TY, int FORCING>
-__global__ __launch_bounds__(64 * TY) void k_moments(const S* __restrict__ src_, S* __restrict__ rho, FluidConsts<S> K,
-                                                      int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
-                                                      S* __restrict__ rec, double* __restrict__ red, uint32_t* status,
-                                                      long long* bad) {
-  using C = S;
+__global__ __launch_bounds__(64 * TY) void k_moments(const S* __restrict__ src_, arith_t<S>* __restrict__ rho,
+                                                      FluidConsts<arith_t<S>> K, int tz, int tiles_x, int xcd,
+                                                      const uint32_t* __restrict__ mask, arith_t<S>* __restrict__ rec,
+                                                      double* __restrict__ red, uint32_t* status, long long* bad) {
+  using C = arith_t<S>;
   __shared__ C ring[4][2][TY + 2][66];
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
   const int64_t plane = int64_t(nx) * ny;
-  const Pops<S> src = make_pops(src_, N);
+  const Pops<S> src = make_pops(src_, N, K.rho0);
   const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
   const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
   double acc[5] = {0, 0, 0, 0, 0};
@@ -643,14 +685,15 @@ __global__ __launch_bounds__(64 * TY) void k_moments(const S* __restrict__ src_,
 // field written by pass P (two values per site instead of 38).
 template <class S, int TY, int FORCING, bool NOISE>
 __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_, S* __restrict__ dst_,
-                                                      const S* __restrict__ rho, FluidConsts<S> K, int tz, int tiles_x,
-                                                      int xcd, const uint32_t* __restrict__ mask, S* __restrict__ gP) {
-  using C = S;
+                                                      const arith_t<S>* __restrict__ rho, FluidConsts<arith_t<S>> K,
+                                                      int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
+                                                      arith_t<S>* __restrict__ gP) {
+  using C = arith_t<S>;
   __shared__ C ring[4][2][TY + 2][66];
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
   const int64_t plane = int64_t(nx) * ny;
-  const Pops<S> src = make_pops(src_, N), dst = make_pops<S>(dst_, N);
+  const Pops<S> src = make_pops(src_, N, K.rho0), dst = make_pops<S>(dst_, N, K.rho0);
   const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
   const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
 
@@ -725,19 +768,21 @@ __global__ void k_finalize(const double* __restrict__ rf, int64_t nf, const doub
 
 // ------------------------------------------------------------ launchers
 template <class S>
-FluidConsts<S> consts(const lbmd_ctx* h) {
-  FluidConsts<S> K;
+FluidConsts<arith_t<S>> consts(const lbmd_ctx* h) {
+  using C = arith_t<S>;
+  FluidConsts<C> K;
   K.nx = h->p.nx;
   K.ny = h->p.ny;
   K.nz = h->p.nz;
   K.N = h->N;
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) K.G[a][b] = S(h->p.G[a][b]);
+    for (int b = 0; b < 2; ++b) K.G[a][b] = C(h->p.G[a][b]);
   for (int c = 0; c < 2; ++c) {
-    K.tau[c] = S(h->p.tau[c]);
-    K.omega[c] = S(1.0 / h->p.tau[c]);
+    K.tau[c] = C(h->p.tau[c]);
+    K.omega[c] = C(1.0 / h->p.tau[c]);
   }
-  K.kT = S(h->p.kT);
+  K.kT = C(h->p.kT);
+  K.rho0 = Storage<S>::deviation ? C(h->p.rho0) : C(0);
   K.forcing = h->p.forcing;
   K.noise = h->p.kT > 0.0;
   K.seed = h->p.seed;
@@ -754,36 +799,39 @@ template <class S>
 static hipError_t init_t(lbmd_ctx* h, const double* rho_dev) {
   const int64_t N = h->N;
   hipLaunchKernelGGL(k_init<S>, dim3((N + 255) / 256), dim3(256), 0, h->stream, (S*)h->f[h->cur], rho_dev, h->p.nx,
-                     h->p.ny, h->p.nz);
+                     h->p.ny, h->p.nz, h->p.rho0);
   return hipGetLastError();
 }
-hipError_t fluid_init(lbmd_ctx* h, const double* rho_dev) {
-  return h->p.precision == LBMD_FP64 ? init_t<double>(h, rho_dev) : init_t<float>(h, rho_dev);
-}
+// calls FN<storage type>(args...) for the handle's precision
+#define LBMD_BY_STORAGE(FN, ...)                                        \
+  switch (h->p.precision) {                                              \
+    case LBMD_FP64: return FN<double>(__VA_ARGS__);                      \
+    case LBMD_FP16DEV: return FN<half_dev>(__VA_ARGS__);                 \
+    case LBMD_BF16DEV: return FN<bf16_dev>(__VA_ARGS__);                 \
+    default: return FN<float>(__VA_ARGS__);                              \
+  }
+hipError_t fluid_init(lbmd_ctx* h, const double* rho_dev) { LBMD_BY_STORAGE(init_t, h, rho_dev) }
 
 template <class S>
 static hipError_t import_t(lbmd_ctx* h, const double* pop) {
   const int64_t N = h->N;
   hipLaunchKernelGGL(k_import<S>, dim3((N + 255) / 256), dim3(256), 0, h->stream, (S*)h->f[h->cur], pop, h->p.nx,
-                     h->p.ny, h->p.nz);
+                     h->p.ny, h->p.nz, h->p.rho0);
   return hipGetLastError();
 }
-hipError_t fluid_import(lbmd_ctx* h, const double* pop) {
-  return h->p.precision == LBMD_FP64 ? import_t<double>(h, pop) : import_t<float>(h, pop);
-}
+hipError_t fluid_import(lbmd_ctx* h, const double* pop) { LBMD_BY_STORAGE(import_t, h, pop) }
 
 template <class S>
 static hipError_t export_t(lbmd_ctx* h, uint32_t mask, double* out) {
+  using C = arith_t<S>;
   const S* src = (const S*)h->f[h->cur];
-  hipLaunchKernelGGL(k_density<S>, plane_grid(h), dim3(256), 0, h->stream, src, (S*)h->rho, h->p.nx, h->p.ny,
-                     h->p.nz);
-  hipLaunchKernelGGL(k_export<S>, plane_grid(h), dim3(256), 0, h->stream, src, (const S*)h->rho, out, consts<S>(h),
-                     mask);
+  const FluidConsts<C> K = consts<S>(h);
+  hipLaunchKernelGGL(k_density<S>, plane_grid(h), dim3(256), 0, h->stream, src, (C*)h->rho, h->p.nx, h->p.ny,
+                     h->p.nz, K.rho0);
+  hipLaunchKernelGGL(k_export<S>, plane_grid(h), dim3(256), 0, h->stream, src, (const C*)h->rho, out, K, mask);
   return hipGetLastError();
 }
-hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out) {
-  return h->p.precision == LBMD_FP64 ? export_t<double>(h, mask, out) : export_t<float>(h, mask, out);
-}
+hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out) { LBMD_BY_STORAGE(export_t, h, mask, out) }
 
 // organisation actually used this step
 static int organisation(const lbmd_ctx* h) {
@@ -844,9 +892,10 @@ static Launch tiles(lbmd_ctx* h) {
 
 template <class S, int FORCING, bool NOISE>
 static hipError_t pass_a_t(lbmd_ctx* h) {
+  using C = arith_t<S>;
   const S* src = (const S*)h->f[h->cur];
   S* dst = (S*)h->f[1 - h->cur];
-  const FluidConsts<S> K = consts<S>(h);
+  const FluidConsts<C> K = consts<S>(h);
   const Launch L = tiles(h);
   h->red_fluid_used = L.nblk;
   const uint32_t* mask = h->np > 0 ? h->mask : nullptr;
@@ -854,17 +903,17 @@ static hipError_t pass_a_t(lbmd_ctx* h) {
     if (hipError_t e = prof_begin(h)) return e;
     if (h->hold) {
       LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_fused<S, TYV, FORCING, NOISE, true>), dim3(L.nblk), dim3(64 * TYV), 0,
-                                          h->stream, src, dst, K, L.tz, L.tiles_x, h->xcd, mask, (S*)h->rec, h->red_fluid,
+                                          h->stream, src, dst, K, L.tz, L.tiles_x, h->xcd, mask, (C*)h->rec, h->red_fluid,
                                           h->status, h->bad_step));
     } else {
       LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_fused<S, TYV, FORCING, NOISE, false>), dim3(L.nblk), dim3(64 * TYV), 0,
-                                          h->stream, src, dst, K, L.tz, L.tiles_x, h->xcd, mask, (S*)h->rec, h->red_fluid,
+                                          h->stream, src, dst, K, L.tz, L.tiles_x, h->xcd, mask, (C*)h->rec, h->red_fluid,
                                           h->status, h->bad_step));
     }
     if (hipError_t e = prof_end(h)) return e;
   } else {
     LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_moments<S, TYV, FORCING>), dim3(L.nblk), dim3(64 * TYV), 0, h->stream, src,
-                                        (S*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (S*)h->rec, h->red_fluid, h->status,
+                                        (C*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (C*)h->rec, h->red_fluid, h->status,
                                         h->bad_step));
   }
   return hipGetLastError();
@@ -872,19 +921,20 @@ static hipError_t pass_a_t(lbmd_ctx* h) {
 
 template <class S, int FORCING, bool NOISE>
 static hipError_t pass_b_t(lbmd_ctx* h) {
+  using C = arith_t<S>;
   const S* src = (const S*)h->f[h->cur];
   S* dst = (S*)h->f[1 - h->cur];
-  const FluidConsts<S> K = consts<S>(h);
+  const FluidConsts<C> K = consts<S>(h);
   if (organisation(h) == LBMD_KERNEL_FUSED) {
     if (h->np > 0)
       hipLaunchKernelGGL((k_fix<S, FORCING, NOISE>), dim3((h->flag_cap + 255) / 256), dim3(256), 0, h->stream, src,
-                         dst, K, h->flag_list, h->nflag, (const S*)h->rec, (S*)h->gP, h->mask);
+                         dst, K, h->flag_list, h->nflag, (const C*)h->rec, (C*)h->gP, h->mask);
   } else {
     const Launch L = tiles(h);
     const uint32_t* mask = h->np > 0 ? h->mask : nullptr;
     if (hipError_t e = prof_begin(h)) return e;
     LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_collide<S, TYV, FORCING, NOISE>), dim3(L.nblk), dim3(64 * TYV), 0,
-                                        h->stream, src, dst, (const S*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (S*)h->gP));
+                                        h->stream, src, dst, (const C*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (C*)h->gP));
     if (hipError_t e = prof_end(h)) return e;
     if (h->np > 0) {
       const int64_t words = (h->N + 31) / 32;
@@ -894,20 +944,24 @@ static hipError_t pass_b_t(lbmd_ctx* h) {
   return hipGetLastError();
 }
 
-#define LBMD_DISPATCH(NAME)                                                                      \
-  hipError_t fluid_##NAME(lbmd_ctx* h) {                                                         \
-    const bool noise = h->p.kT > 0.0;                                                            \
-    if (h->p.precision == LBMD_FP64) {                                                           \
-      if (h->p.forcing == LBMD_FORCE_SHIFT) return NAME##_t<double, LBMD_FORCE_SHIFT, false>(h); \
-      return noise ? NAME##_t<double, LBMD_FORCE_PAPER, true>(h)                                 \
-                   : NAME##_t<double, LBMD_FORCE_PAPER, false>(h);                               \
-    }                                                                                            \
-    if (h->p.forcing == LBMD_FORCE_SHIFT) return NAME##_t<float, LBMD_FORCE_SHIFT, false>(h);    \
-    return noise ? NAME##_t<float, LBMD_FORCE_PAPER, true>(h) : NAME##_t<float, LBMD_FORCE_PAPER, false>(h); \
+#define LBMD_DISPATCH_S(NAME, S)                                                         \
+  if (h->p.forcing == LBMD_FORCE_SHIFT) return NAME##_t<S, LBMD_FORCE_SHIFT, false>(h); \
+  return noise ? NAME##_t<S, LBMD_FORCE_PAPER, true>(h) : NAME##_t<S, LBMD_FORCE_PAPER, false>(h);
+#define LBMD_DISPATCH(NAME)                                     \
+  hipError_t fluid_##NAME(lbmd_ctx* h) {                        \
+    const bool noise = h->p.kT > 0.0;                           \
+    switch (h->p.precision) {                                   \
+      case LBMD_FP64: { LBMD_DISPATCH_S(NAME, double) }         \
+      case LBMD_FP16DEV: { LBMD_DISPATCH_S(NAME, half_dev) }    \
+      case LBMD_BF16DEV: { LBMD_DISPATCH_S(NAME, bf16_dev) }    \
+      default: { LBMD_DISPATCH_S(NAME, float) }                 \
+    }                                                           \
   }
 LBMD_DISPATCH(pass_a)
 LBMD_DISPATCH(pass_b)
 #undef LBMD_DISPATCH
+#undef LBMD_DISPATCH_S
+#undef LBMD_BY_STORAGE
 
 hipError_t finalize_step(lbmd_ctx* h) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->red_fluid, h->red_fluid_used, h->red_part,

@@ -25,6 +25,45 @@ __host__ __device__ constexpr C weight(int i) {
   return i == 0 ? C(1) / C(3) : (i <= 6 ? C(1) / C(18) : C(1) / C(36));
 }
 
+// ------------------------------------------------------------ storage types
+// Population storage.  float and double hold f itself and are also the
+// arithmetic type.  dev16<IEEE> holds the deviation f_i - w_i rho0 in 16 bits
+// (IEEE binary16 or bfloat16, round to nearest even) with float arithmetic:
+// near the rest state the deviation is a few per cent of w_i rho0, so the
+// 16-bit mantissa is spent on the part of f that changes.
+template <bool IEEE>
+struct dev16 {
+  uint16_t bits;
+};
+using half_dev = dev16<true>;
+using bf16_dev = dev16<false>;
+
+template <class S>
+struct Storage {
+  using C = S;  // arithmetic type
+  static constexpr bool deviation = false;
+};
+template <bool IEEE>
+struct Storage<dev16<IEEE>> {
+  using C = float;
+  static constexpr bool deviation = true;
+};
+template <class S>
+using arith_t = typename Storage<S>::C;
+
+__device__ __forceinline__ float dev_decode(uint16_t b, dev16<true>*) {
+  return float(__builtin_bit_cast(_Float16, b));
+}
+__device__ __forceinline__ float dev_decode(uint16_t b, dev16<false>*) {
+  return float(__builtin_bit_cast(__bf16, b));
+}
+__device__ __forceinline__ uint16_t dev_encode(float v, dev16<true>*) {
+  return __builtin_bit_cast(uint16_t, _Float16(v));
+}
+__device__ __forceinline__ uint16_t dev_encode(float v, dev16<false>*) {
+  return __builtin_bit_cast(uint16_t, __bf16(v));
+}
+
 // ------------------------------------------------------------ Philox4x32-10
 // Counter-based generator of Salmon et al. (SC'11): ten rounds; each round
 // multiplies words 0 and 2 by fixed 32-bit constants, xors the high halves
@@ -108,6 +147,7 @@ struct FluidConsts {
   uint64_t seed;
   int64_t step;
   int nt;  // non-temporal hint on the population stores
+  C rho0;  // reference density of deviation storage (0 otherwise)
 };
 
 }  // namespace lbmd
@@ -121,6 +161,7 @@ struct lbmd_ctx {
   hipStream_t side = nullptr;  // second stream: pair forces next to the density pass
   hipEvent_t ev_sorted = nullptr, ev_pairs = nullptr;
   size_t s_bytes = 8;  // bytes per stored population
+  size_t c_bytes = 8;  // bytes per arithmetic value (density field, records, node forces)
 
   // fluid state: populations in the pull layout (buffer value at s for
   // velocity i streams to s + c_i at the next step)

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "liblbmd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
-FP64, FP32 = 0, 1
+FP64, FP32, FP16DEV, BF16DEV = 0, 1, 2, 3
 FORCE_PAPER, FORCE_SHIFT = 0, 1
 KERNEL_FUSED, KERNEL_TWOPASS, KERNEL_AUTO = 0, 1, 2
 RHO, U, POP = 1, 2, 4
@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double * 2), ("G", (ctypes.c_double * 2) * 2),
         ("gamma", ctypes.c_double), ("kappa", ctypes.c_double * 2), ("mass", ctypes.c_double),
         ("kT", ctypes.c_double), ("seed", ctypes.c_uint64),
-        ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rho0", ctypes.c_double),
     ]
 
 
@@ -100,7 +100,7 @@ class Sim:
 
     def __init__(self, shape, precision=FP32, forcing=FORCE_PAPER, kernel=KERNEL_AUTO, tau=(1.0, 1.0),
                  G=((0.0, 1.6), (1.6, 0.0)), gamma=0.0, kappa=(0.0, 0.0), mass=1.0, kT=0.0, seed=0,
-                 check_every=0, rho_init=None, stream=None):
+                 check_every=0, rho_init=None, stream=None, rho0=1.0):
         L = load()
         p = Params()
         p.nx, p.ny, p.nz = (int(s) for s in shape)
@@ -112,6 +112,7 @@ class Sim:
         p.gamma = gamma
         p.kappa[0], p.kappa[1] = kappa
         p.mass, p.kT, p.seed, p.check_every = mass, kT, seed, check_every
+        p.rho0 = rho0
         self.shape = tuple(int(s) for s in shape)
         self.N = int(np.prod(self.shape))
         self.params = p

@@ -53,8 +53,9 @@ def test_params_struct_layout_matches_header():
     compiler on the header)."""
     from paper_1306_0788_amd import lbmd
     src = ('#include "lbmd.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-           'int main(){printf("%zu %zu %zu %zu\\n", sizeof(lbmd_params), offsetof(lbmd_params, tau),'
-           ' offsetof(lbmd_params, seed), offsetof(lbmd_params, check_every));return 0;}\n')
+           'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(lbmd_params), offsetof(lbmd_params, tau),'
+           ' offsetof(lbmd_params, seed), offsetof(lbmd_params, check_every), offsetof(lbmd_params, rho0));'
+           'return 0;}\n')
     import tempfile
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
@@ -62,5 +63,5 @@ def test_params_struct_layout_matches_header():
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", os.path.join(d, "t")])
         got = subprocess.run([os.path.join(d, "t")], capture_output=True, text=True).stdout.split()
     P = lbmd.Params
-    want = [ctypes.sizeof(P), P.tau.offset, P.seed.offset, P.check_every.offset]
+    want = [ctypes.sizeof(P), P.tau.offset, P.seed.offset, P.check_every.offset, P.rho0.offset]
     assert [int(g) for g in got] == want
