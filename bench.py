@@ -137,6 +137,74 @@ def copy_calibration():
                       "ms": round(ms, 4), "GBs_read_plus_write": round(2 * n * 4 / ms / 1e6, 1)}), flush=True)
 
 
+def interface(phi, shape):
+    """Interface of phi = rho_A - rho_B on the periodic lattice (the locus
+    rho_A = rho_B): per axis, the links across which phi changes sign and the
+    linear zero crossing along each (fraction of the link from its lower
+    site).  Returns {axis: (link mask, crossing)}."""
+    nx, ny, nz = shape
+    f = phi.reshape(nz, ny, nx)
+    out = {}
+    for ax, npax in (("x", 2), ("y", 1), ("z", 0)):
+        g = np.roll(f, -1, axis=npax)
+        m = (f > 0) != (g > 0)
+        t = np.where(m, f / np.where(m, f - g, 1.0), 0.0)
+        out[ax] = (m, t)
+    return out
+
+
+def accuracy_study(workload, steps):
+    """Error of each storage form against the FP64 step after `steps` steps of
+    the workload (same seeded inputs): density of A, coupling velocity u_c,
+    interface area (links across which rho_A - rho_B changes sign) and
+    position (zero crossing along the links both runs cut), and the mass
+    drift of each component from the device FP64 sums."""
+    import torch
+    from paper_1306_0788_amd import lbmd
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    res = {}
+    ref = None
+    for prec in ("fp64", "fp32", "fp16dev", "bf16dev"):
+        print("accuracy: %s %s, %d steps" % (workload, prec, steps), file=sys.stderr, flush=True)
+        sim, w, npart = setup(workload, stream.cuda_stream, lbmd.KERNEL_AUTO, None, prec)
+        sim.step(1)
+        r0, _ = sim.reductions()
+        sim.step(steps - 1)
+        rc = sim.sync()
+        if rc != lbmd.OK:
+            res[prec] = {"failed": sim.last_error()}
+            sim.close()
+            continue
+        r1, _ = sim.reductions()
+        fields = sim.get_fields(lbmd.RHO | lbmd.U)
+        sim.close()
+        N = int(np.prod(w["shape"]))
+        rho = fields[:2 * N].reshape(2, N)
+        u = fields[2 * N:].reshape(3, N)
+        itf = interface(rho[0] - rho[1], w["shape"])
+        area = int(sum(int(m.sum()) for m, _ in itf.values()))
+        drift = [float(abs(r1[c] - r0[c]) / r0[c]) for c in range(2)]
+        if ref is None:
+            ref = (rho, u, itf, area)
+            res[prec] = {"interface_links": area, "mass_drift": drift}
+            continue
+        rr, ur, itr, ar = ref
+        both = [(m & itr[ax][0], t, itr[ax][1]) for ax, (m, t) in itf.items()]
+        nboth = sum(int(b.sum()) for b, _, _ in both)
+        pos_err = sum(float(np.abs(t[b] - tr[b]).sum()) for b, t, tr in both) / max(nboth, 1)
+        dr = rho[0] - rr[0]
+        du = u - ur
+        res[prec] = {"rho_A_max_abs_err": float(np.abs(dr).max()), "rho_A_rms_err": float(np.sqrt(np.mean(dr ** 2))),
+                     "u_max_abs_err": float(np.abs(du).max()), "u_rms_err": float(np.sqrt(np.mean(du ** 2))),
+                     "u_max_abs_ref": float(np.abs(ur).max()),
+                     "interface_links": area, "interface_links_rel_diff": (area - ar) / max(ar, 1),
+                     "interface_position_mean_abs_diff": pos_err, "mass_drift": drift}
+        del rho, u, itf
+    print(json.dumps({"accuracy": workload, "steps": steps, "reference": "fp64 GPU step (parity-tested "
+                      "against the FP64 oracle)", "results": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,11 +218,16 @@ def main():
                     help="population storage (default: the workload's); fp16dev / bf16dev store f - w rho0")
     ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("TILE_Y", "TILE_Z"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy", type=int, default=None, metavar="STEPS",
+                    help="instead of timing: error of every storage form against the FP64 step after STEPS steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 2 GiB copy kernel used to calibrate the byte counters")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.accuracy is not None:
+        accuracy_study(args.workload, args.accuracy)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the path shards by z-slabs across GPUs, "

@@ -44,11 +44,13 @@ struct Pops {
   __amdgpu_buffer_rsrc_t r[2];
   uint32_t pstride;  // N * sizeof(S)
   arith_t<S> rho0;   // deviation storage: w_i rho0 is added on load, removed on store
+  uint32_t srkey;    // deviation storage: key of the stochastic rounding
 };
 template <class S>
-__device__ __forceinline__ Pops<S> make_pops(const S* base, int64_t N, arith_t<S> rho0 = 0) {
+__device__ __forceinline__ Pops<S> make_pops(const S* base, int64_t N, arith_t<S> rho0 = 0, uint32_t srkey = 0) {
   Pops<S> p;
   p.rho0 = rho0;
+  p.srkey = srkey;
   const uint32_t bytes = uint32_t(19 * N * int64_t(sizeof(S)));
 #pragma unroll
   for (int c = 0; c < 2; ++c)
@@ -88,11 +90,12 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint3
                                         int(vo), int(so), AUX);
 }
 
-// store population i of component c at byte offset vo (AUX as above)
+// store population i of component c at byte offset vo (AUX as above);
+// r: random bits for the stochastic rounding of a deviation
 template <int AUX, class S>
-__device__ __forceinline__ void put_pop(const Pops<S>& p, int c, uint32_t vo, int i, arith_t<S> v) {
+__device__ __forceinline__ void put_pop(const Pops<S>& p, int c, uint32_t vo, int i, arith_t<S> v, uint32_t r) {
   if constexpr (Storage<S>::deviation) {
-    const uint16_t b = dev_encode(v - weight<float>(i) * p.rho0, (S*)nullptr);
+    const uint16_t b = dev_encode_sr(v - weight<float>(i) * p.rho0, r, (S*)nullptr);
     __builtin_amdgcn_raw_buffer_store_b16(b, p.r[c], int(vo), int(uint32_t(i) * p.pstride), AUX);
   } else {
     bstore<AUX>(S(v), p.r[c], vo, uint32_t(i) * p.pstride);
@@ -118,19 +121,25 @@ __device__ __forceinline__ void pull(const Pops<S>& src, int x, int y, int z, in
   }
 }
 
+// Stores the 38 post-collision populations of site s.  Deviation storage
+// draws 32 random bits per velocity (16 per component) from the site, the
+// velocity and the step key: the same on every tiling and every run.
 template <class S, class C>
 __device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&f)[2][19], bool nt = true) {
   const uint32_t vo = s * uint32_t(sizeof(S));
-  if (nt) {
+  uint32_t hs = 0;
+  if constexpr (Storage<S>::deviation) hs = mix32(s ^ dst.srkey);
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int i = 0; i < 19; ++i) put_pop<2>(dst, c, vo, i, arith_t<S>(f[c][i]));
-  } else {
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int i = 0; i < 19; ++i) put_pop<0>(dst, c, vo, i, arith_t<S>(f[c][i]));
+  for (int i = 0; i < 19; ++i) {
+    uint32_t r = 0;
+    if constexpr (Storage<S>::deviation) r = mix32(hs + uint32_t(i) * 0x9E3779B9u);
+    if (nt) {
+      put_pop<2>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
+      put_pop<2>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
+    } else {
+      put_pop<0>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
+      put_pop<0>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
+    }
   }
 }
 
@@ -450,7 +459,7 @@ __global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
   const int64_t plane = int64_t(nx) * ny;
-  const Pops<S> src = make_pops(src_, N, K.rho0), dst = make_pops<S>(dst_, N, K.rho0);
+  const Pops<S> src = make_pops(src_, N, K.rho0), dst = make_pops<S>(dst_, N, K.rho0, K.srkey);
   const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
   const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
 
@@ -575,7 +584,7 @@ __global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __res
   }
   mask[s >> 5] = 0u;
   collide<C, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s));
-  store<S, C>(make_pops<S>(dst, N, K.rho0), uint32_t(s), f);
+  store<S, C>(make_pops<S>(dst, N, K.rho0, K.srkey), uint32_t(s), f);
 }
 
 // ------------------------------------------------------------ split path
@@ -693,7 +702,7 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
   const int64_t plane = int64_t(nx) * ny;
-  const Pops<S> src = make_pops(src_, N, K.rho0), dst = make_pops<S>(dst_, N, K.rho0);
+  const Pops<S> src = make_pops(src_, N, K.rho0), dst = make_pops<S>(dst_, N, K.rho0, K.srkey);
   const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
   const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
 
@@ -783,6 +792,8 @@ FluidConsts<arith_t<S>> consts(const lbmd_ctx* h) {
   }
   K.kT = C(h->p.kT);
   K.rho0 = Storage<S>::deviation ? C(h->p.rho0) : C(0);
+  K.srkey = mix32(uint32_t(h->step) ^ mix32(uint32_t(uint64_t(h->step) >> 32) ^ mix32(uint32_t(h->p.seed) ^
+                                                                                   uint32_t(h->p.seed >> 32))));
   K.forcing = h->p.forcing;
   K.noise = h->p.kT > 0.0;
   K.seed = h->p.seed;

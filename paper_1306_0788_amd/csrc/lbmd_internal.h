@@ -64,6 +64,38 @@ __device__ __forceinline__ uint16_t dev_encode(float v, dev16<false>*) {
   return __builtin_bit_cast(uint16_t, __bf16(v));
 }
 
+// 32-bit integer mixer (the "lowbias32" hash of C. Wellons' hash-prospector
+// search: xor-shift / multiply rounds, a bijection with low avalanche bias).
+__host__ __device__ constexpr uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Stochastic rounding of a stored deviation: r (16 random bits) is added
+// below the kept mantissa bits of |v| and the rest truncated, so the stored
+// value rounds up with probability equal to the discarded fraction and is
+// unbiased per value.  Round-to-nearest would err the same way at every
+// site of a nearly uniform phase (the deviations there all sit near one
+// value) and drift the mass coherently.  Non-finite values round to nearest.
+__device__ __forceinline__ uint16_t dev_encode_sr(float v, uint32_t r, dev16<false>*) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, v);
+  if ((b & 0x7f800000u) == 0x7f800000u) return dev_encode(v, (dev16<false>*)nullptr);
+  return uint16_t((b + (r & 0xffffu)) >> 16);  // bfloat16 keeps the top 16 bits
+}
+__device__ __forceinline__ uint16_t dev_encode_sr(float v, uint32_t r, dev16<true>*) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, v);
+  if ((b & 0x7f800000u) == 0x7f800000u) return dev_encode(v, (dev16<true>*)nullptr);
+  // binary16 keeps 10 of the 23 mantissa bits: randomise the low 13 and
+  // truncate; the conversion of the truncated float is then exact in the
+  // normal range of binary16 (below it, about 6e-5, it rounds to nearest)
+  const uint32_t t = (b + (r & 0x1fffu)) & ~0x1fffu;
+  return dev_encode(__builtin_bit_cast(float, t), (dev16<true>*)nullptr);
+}
+
 // ------------------------------------------------------------ Philox4x32-10
 // Counter-based generator of Salmon et al. (SC'11): ten rounds; each round
 // multiplies words 0 and 2 by fixed 32-bit constants, xors the high halves
@@ -148,6 +180,7 @@ struct FluidConsts {
   int64_t step;
   int nt;  // non-temporal hint on the population stores
   C rho0;  // reference density of deviation storage (0 otherwise)
+  uint32_t srkey;  // per-step key of the stochastic rounding of deviations
 };
 
 }  // namespace lbmd

@@ -57,6 +57,13 @@ WORKLOADS = {
                    kappa=((0.05, 0.0),), mass=(100.0,), charge=(0.0,),
                    particles=dict(kind="free", n=160000, min_dist=WCA_CUT), wca=(1.0, 1.0),
                    fene=None, dh=None, steps=200, onset=117),
+    # The same at G_AB = 1.4 (still phase separating, no density reaches
+    # zero within 1,000 steps): the long comparison of the storage forms.
+    "c2_256_g14": dict(shape=(256, 256, 256), precision="fp32", forcing="paper", tau=(1.0, 1.0),
+                       G=((0.0, 1.4), (1.4, 0.0)), gamma=1.0, kT=0.0, seed=6,
+                       kappa=((0.05, 0.0),), mass=(100.0,), charge=(0.0,),
+                       particles=dict(kind="free", n=160000, min_dist=WCA_CUT), wca=(1.0, 1.0),
+                       fene=None, dh=None, steps=1000, onset=None),
 }
 
 

@@ -2,22 +2,24 @@
 f_i - w_i rho0 in IEEE binary16 (FP16DEV) or bfloat16 (BF16DEV), all
 arithmetic in FP32, compared with the FP64 oracle on the same seeded inputs.
 
-Tolerances.  A stored deviation d_i = f_i - w_i rho0 is rounded to nearest,
-so it carries an error of at most u |d_i| with u = 2^-11 (binary16) or 2^-8
-(bfloat16).  Write D = max over sites and velocities of |d_i| / w_i, the
-largest deviation in density units.  One step reads rounded inputs (density
-and momentum errors <= u D, spread to every population of the site by the
-equilibrium, plus the Shan-Chen neighbour sums, whose weights sum to 1 per
-component: another G u D) and rounds its outputs (u D w_i).  So after one
-step |f_gpu - f_oracle| / w_i <= (2 + 2 G) u D; the tests allow 4 u D at
-G <= 1.6 (factor ~1 of margin).  Particle forces inherit the node errors
-through the interpolation weights (sum 1): the friction part by gamma times
-the velocity error (about 3 u D at rho ~ 1), the solvation part by
-3 sum|kappa| times the neighbour-sum error (about u D, the stencil weights
-summing to 1); the tests allow 4 times (3 gamma + 3 sum|kappa|) u D.  Over
-many steps the error grows with the Shan-Chen modes (x40 per 100 steps at
-G rho = 1.6, as the FP64 round-off does); the 100-step bounds are that
-growth times the one-step bound.
+Tolerances.  The initial state is rounded to nearest (error <= u |d_i|,
+u = 2^-11 for binary16, 2^-8 for bfloat16, d_i = f_i - w_i rho0); every
+step stores its output with stochastic rounding (error < 1 ulp = 2 u |d_i|,
+unbiased).  Write D = max |d_i| / w_i over sites and velocities (the largest
+deviation in density units).  With tau = 1 a step's output depends on its
+inputs only through rho, j and the Shan-Chen force: input errors move rho by
+at most u D, each momentum component by u D / 3 (sum_i w_i |c_ix| = 1/3)
+and the neighbour sums by u D / 3, so population i moves by at most
+w_i u D (1 + |c_i|_1 (1 + G/2)) (|c_i|_1 <= 2); adding the output rounding,
+|f_gpu - f_oracle| / w_i < (3 + 2 (1 + G/2)) u D after one step: 6.6 u D at
+G = 1.6, 6.3 u D at G = 1.3; the tests allow 7 u D.  Particle forces
+inherit the node errors through the interpolation weights (sum 1): the
+friction part by gamma times the velocity error (about 3 u D at rho ~ 1),
+the solvation part by 3 sum|kappa| times the neighbour-sum error (about
+u D); the tests allow 4 times (3 gamma + 3 sum|kappa|) u D.  Over many steps
+the error grows with the Shan-Chen modes (x40 per 100 steps at G rho = 1.6,
+as the FP64 round-off does); the 100-step bounds are 100 times the one-step
+bound.
 """
 import numpy as np
 import pytest
@@ -66,7 +68,7 @@ def test_one_step_against_oracle(precision, kernel):
     D = max(weighted_dev(f0), weighted_dev(f1))
     err = weighted_err(g.populations(), f1)
     print("D = %.4g, weighted population error %.3e = %.2f u D" % (D, err, err / (u * D)), flush=True)
-    assert err <= 4 * u * D
+    assert err <= 7 * u * D
     x, v, F, Fc = g.particles()
     fscale = (3 * 0.5 + 3 * (0.3 + 0.2)) * u * D  # 3 gamma u D + 3 sum|kappa| u D
     eF = np.abs(Fc - o.Fc).max()
@@ -85,7 +87,7 @@ def test_ragged_shapes(shape, precision):
     D = max(weighted_dev(f0), weighted_dev(f1))
     err = weighted_err(g.populations(), f1)
     print("ragged %s: %.2f u D" % (shape, err / (UNIT[precision] * D)), flush=True)
-    assert err <= 4 * UNIT[precision] * D
+    assert err <= 7 * UNIT[precision] * D
 
 
 @pytest.mark.parametrize("precision,growth", [(FP16DEV, 100.0), (BF16DEV, 100.0)])
@@ -104,17 +106,17 @@ def test_hundred_steps_density(precision, growth, kernel):
     g32.step(100)
     e32 = float(np.abs(g32.rho() - o.rho()).max())
     print("100 steps: max |rho - rho_oracle| %.3e (FP32 %.3e), D = %.3g, bound %.3e"
-          % (e, e32, D, growth * 4 * UNIT[precision] * D), flush=True)
-    assert e <= growth * 4 * UNIT[precision] * D
+          % (e, e32, D, growth * 7 * UNIT[precision] * D), flush=True)
+    assert e <= growth * 7 * UNIT[precision] * D
 
 
 @pytest.mark.parametrize("precision", [FP16DEV, BF16DEV])
 def test_mass_drift_is_rounding_sized(precision):
-    """Rounding the stored deviations is not mass-conserving.  Round to nearest
-    is unbiased, so the total mass of a component performs a random walk of
-    step ~ u D w sqrt(19 N) per step; after n steps its drift stays below
-    n u D sqrt(19 N) / 19 (the mean absolute drift of n coherent roundings,
-    an upper bound for the walk), relative to the mass N rho."""
+    """Rounding the stored deviations is not mass-conserving.  Stochastic
+    rounding is unbiased per value, so the total mass of a component performs
+    a random walk of step ~ 2 u D w sqrt(19 N) per step; after n steps its
+    drift stays below n 2 u D sqrt(19 N) / 19 (n steps of that size in one
+    direction, an upper bound for the walk), relative to the mass N rho."""
     shape = (24, 20, 16)
     c = Case(shape, precision, lbmd.FORCE_PAPER, lbmd.KERNEL_TWOPASS, G=1.4, gamma=0.8, npart=50, vel_amp=0.05,
              kappa=((0.3, -0.1),), mass=(400.0,), wca=(1.0, 0.05), min_dist=1.3)
@@ -126,7 +128,7 @@ def test_mass_drift_is_rounding_sized(precision):
     r1, _ = g.reductions()
     N = c.N
     D = max(weighted_dev(g.populations()), 0.01)
-    bound = n * UNIT[precision] * D * np.sqrt(19 * N) / 19 / N
+    bound = n * 2 * UNIT[precision] * D * np.sqrt(19 * N) / 19 / N
     for comp in range(2):
         drift = abs(r1[comp] - r0[comp]) / r0[comp]
         print("component %d: relative mass drift over %d steps %.3e (bound %.3e)" % (comp, n, drift, bound),
@@ -139,3 +141,17 @@ def test_rejects_bad_reference_density():
         lbmd.Sim((8, 8, 8), precision=FP16DEV, rho0=0.0)
     with pytest.raises(lbmd.LbmdError):
         lbmd.Sim((8, 8, 8), precision=BF16DEV, rho0=float("nan"))
+
+
+@pytest.mark.parametrize("precision", [FP16DEV, BF16DEV])
+def test_stochastic_rounding_is_reproducible_across_tilings(precision):
+    """The rounding draws depend only on the site, the velocity and the step,
+    so two tilings of the same organisation give identical bits."""
+    c = Case((37, 29, 23), precision, lbmd.FORCE_PAPER, lbmd.KERNEL_FUSED, G=1.4, npart=0)
+    a = c.gpu_sim()
+    b = c.gpu_sim()
+    a.set_tiling(4, 16, 1, 0, 1)
+    b.set_tiling(8, 5, 0, 1, 1)
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(a.populations(), b.populations())
