@@ -236,6 +236,29 @@ int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t*
    handle. */
 int lbmd_organisation(lbmd_handle h);
 
+/* Replay of captured step sequences (default off).  With enable != 0,
+   lbmd_step advances two steps at a time by launching a HIP graph captured
+   from the step's own launch sequence (one graph per ping-pong parity,
+   captured on first use, dropped when particles, types, potentials, bonds
+   or the tiling change); an odd remainder, and any step while kernel
+   timing is on, is launched kernel by kernel.  Results are identical to
+   the eager launches.  Waits for the handle's stream.  The caller's stream
+   must not be under capture by someone else.  Errors: LBMD_EINVAL,
+   LBMD_EDEVICE. */
+int lbmd_set_graph(lbmd_handle h, int32_t enable);
+
+/* Tiling autotuner.  Times the fluid passes of the organisation the next
+   step would use, reps times per candidate tiling (rows per tile, planes per
+   z chunk, HOLD and XCD flags; non-temporal stores on), on the current state
+   without advancing it, and keeps the fastest as if set by lbmd_set_tiling.
+   cache_path (may be NULL): a text file of "nx ny nz precision organisation
+   forcing noise tile_y tile_z flags ms" lines; an existing entry for the
+   same key is applied without timing, a new result is appended.  chosen
+   (may be NULL) receives {tile_y, tile_z, flags}; best_ms (may be NULL) the
+   time of one pass pair in ms.  Waits.  Errors: LBMD_EINVAL (reps < 1),
+   LBMD_ESTATE (failure latched), LBMD_EDEVICE. */
+int lbmd_autotune(lbmd_handle h, int32_t reps, const char* cache_path, int32_t* chosen, double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

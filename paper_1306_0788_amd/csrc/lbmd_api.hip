@@ -47,6 +47,15 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+// drop the captured step sequences (the launch sequence changed)
+void graph_invalidate(lbmd_ctx* h) {
+  for (int c = 0; c < 2; ++c)
+    if (h->gexec[c]) {
+      (void)hipGraphExecDestroy(h->gexec[c]);
+      h->gexec[c] = nullptr;
+    }
+}
+
 bool finite_all(const double* a, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(a[i])) return false;
@@ -204,6 +213,161 @@ hipError_t prof_end(lbmd_ctx* h) {
 }
 }  // namespace lbmd
 
+namespace {
+
+// Launch sequence of one step (see lbmd_step); flips nothing.
+int enqueue_step(lbmd_ctx* h) {
+  const bool parts = h->np > 0;
+  if (parts) {
+    HIPCHECK(h, particles_begin(h));
+    HIPCHECK(h, particles_pairs(h));
+  } else {
+    h->red_part_used = 0;
+  }
+  HIPCHECK(h, fluid_pass_a(h));
+  if (parts) HIPCHECK(h, particles_forces(h));
+  HIPCHECK(h, fluid_pass_b(h));
+  if (parts) HIPCHECK(h, particles_end(h));
+  HIPCHECK(h, finalize_step(h));
+  return LBMD_OK;
+}
+
+// Capture two steps from the current ping-pong parity into an executable
+// graph.  Every step-dependent quantity is read by the kernels from the
+// device step counter, so the graph replays any pair of steps.  The second
+// stream (pair forces) joins the capture through its events.
+int capture_two_steps(lbmd_ctx* h) {
+  const int c0 = h->cur;
+  HIPCHECK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  int rc = LBMD_OK;
+  for (int k = 0; k < 2 && rc == LBMD_OK; ++k) {
+    rc = enqueue_step(h);
+    h->cur = 1 - h->cur;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->stream, &g);
+  h->cur = c0;
+  if (rc != LBMD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return hip_fail(h, ei, "hipGraphInstantiate");
+  h->gexec[c0] = x;
+  return LBMD_OK;
+}
+
+// Tiling search.  Times the two fluid passes of the current organisation
+// (pass a + pass b, the kernels that carry the lattice traffic) for every
+// candidate tiling on the current state, without advancing it: outside a
+// step the touched-node mask, the node forces and the compact node list are
+// empty, so the passes only rewrite the scratch population buffer, the
+// density field and the reduction partials.  The fastest tiling is kept
+// (lbmd_set_tiling semantics) and, with a cache file, recorded under the key
+// (lattice, precision, organisation, forcing, noise); a later call with the
+// same key reads it back instead of timing.
+int autotune(lbmd_ctx* h, int reps, const char* cache_path, int32_t* chosen, double* best_ms) {
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  const int org = organisation_of(h);
+  char key[160];
+  snprintf(key, sizeof key, "%d %d %d %d %d %d %d", h->p.nx, h->p.ny, h->p.nz, h->p.precision, org, h->p.forcing,
+           h->p.kT > 0 ? 1 : 0);
+  auto report = [&](int ty, int tz, int flags, double ms) {
+    if (chosen) {
+      chosen[0] = ty;
+      chosen[1] = tz;
+      chosen[2] = flags;
+    }
+    if (best_ms) *best_ms = ms;
+  };
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char line[256];
+      int found = 0, ty = 0, tz = 0, fl = 0;
+      double ms = 0;
+      const size_t kl = strlen(key);
+      while (fgets(line, sizeof line, f))
+        if (strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
+            sscanf(line + kl, " %d %d %d %lf", &ty, &tz, &fl, &ms) == 4)
+          found = 1;  // the last entry for the key wins
+      fclose(f);
+      if (found && lbmd_set_tiling(h, ty, tz, fl) == LBMD_OK) {
+        report(ty, tz, fl, ms);
+        return LBMD_OK;
+      }
+    }
+  }
+  struct Cand {
+    int ty, tz, flags;
+  };
+  std::vector<Cand> cands;
+  const bool fused = org == LBMD_KERNEL_FUSED;
+  const int tys_f[] = {2, 4, 8}, tys_t[] = {4, 8, 16};
+  const int tzs_f[] = {8, 16, 32}, tzs_t[] = {16, 32, 64, 128};
+  for (int a = 0; a < 3; ++a) {
+    const int ty = fused ? tys_f[a] : tys_t[a];
+    if (ty > std::max(2, h->p.ny) && ty != 2) continue;
+    const int ntz = fused ? 3 : 4;
+    for (int b = 0; b < ntz; ++b) {
+      const int tz = std::min(fused ? tzs_f[b] : tzs_t[b], h->p.nz);
+      for (int xcd = 0; xcd < 2; ++xcd)
+        for (int hold = 0; hold < (fused ? 2 : 1); ++hold) {
+          const Cand c{ty, tz, LBMD_TILE_NT | (xcd ? LBMD_TILE_XCD : 0) | (hold ? LBMD_TILE_HOLD : 0)};
+          bool dup = false;
+          for (const Cand& d : cands) dup = dup || (d.ty == c.ty && d.tz == c.tz && d.flags == c.flags);
+          if (!dup) cands.push_back(c);
+        }
+    }
+  }
+  const bool prof = h->prof_on;
+  h->prof_on = false;
+  hipEvent_t e0, e1;
+  HIPCHECK(h, hipEventCreate(&e0));
+  HIPCHECK(h, hipEventCreate(&e1));
+  double best = 1e300;
+  Cand win = cands.front();
+  int rc = LBMD_OK;
+  for (const Cand& c : cands) {
+    lbmd_set_tiling(h, c.ty, c.tz, c.flags);
+    hipError_t e = fluid_pass_a(h);
+    if (e == hipSuccess) e = fluid_pass_b(h);
+    if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      e = fluid_pass_a(h);
+      if (e == hipSuccess) e = fluid_pass_b(h);
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      rc = hip_fail(h, e, "autotune");
+      break;
+    }
+    if (ms / reps < best) {
+      best = ms / reps;
+      win = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->prof_on = prof;
+  if (rc != LBMD_OK) return rc;
+  lbmd_set_tiling(h, win.ty, win.tz, win.flags);
+  report(win.ty, win.tz, win.flags, best);
+  if (cache_path)
+    if (FILE* f = fopen(cache_path, "a")) {
+      fprintf(f, "%s %d %d %d %.6f\n", key, win.ty, win.tz, win.flags, best);
+      fclose(f);
+    }
+  return LBMD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, lbmd_handle* out) {
@@ -254,13 +418,15 @@ int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, 
   h->red_fluid_cap = std::max<int64_t>(tiles_x * ((p->ny + 1) / 2) * p->nz, tiles_x * ((p->ny + 3) / 4) * p->nz);
   if (dalloc(&h->red_fluid, 5 * h->red_fluid_cap) != hipSuccess) return bail(LBMD_ENOMEM);
   if (dalloc(&h->red_out, 8) != hipSuccess || dalloc(&h->status, 1) != hipSuccess ||
-      dalloc(&h->bad_step, 1) != hipSuccess || dalloc(&h->nflag, 1) != hipSuccess)
+      dalloc(&h->bad_step, 1) != hipSuccess || dalloc(&h->nflag, 1) != hipSuccess ||
+      dalloc(&h->step_dev, 1) != hipSuccess)
     return bail(LBMD_ENOMEM);
   const long long never = 0x7fffffffffffffffLL;
   if (hipMemsetAsync(h->red_out, 0, 8 * sizeof(double), h->stream) != hipSuccess ||
       hipMemsetAsync(h->status, 0, sizeof(uint32_t), h->stream) != hipSuccess ||
       hipMemcpyAsync(h->bad_step, &never, sizeof never, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-      hipMemsetAsync(h->nflag, 0, sizeof(int32_t), h->stream) != hipSuccess)
+      hipMemsetAsync(h->nflag, 0, sizeof(int32_t), h->stream) != hipSuccess ||
+      hipMemsetAsync(h->step_dev, 0, sizeof(int64_t), h->stream) != hipSuccess)
     return bail(LBMD_EDEVICE);
   double* rho_dev = nullptr;
   if (rho_init) {
@@ -296,6 +462,8 @@ int lbmd_destroy(lbmd_handle h) {
   dfree(h->status);
   dfree(h->bad_step);
   dfree(h->nflag);
+  dfree(h->step_dev);
+  graph_invalidate(h);
   dfree(h->export_tmp);
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamSynchronize(h->side);
@@ -309,6 +477,7 @@ int lbmd_destroy(lbmd_handle h) {
 
 int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double* vel, const int32_t* type) {
   if (!h || n < 0 || (n > 0 && !pos)) return fail(h, LBMD_EINVAL, "set_particles: bad arguments");
+  graph_invalidate(h);
   if (n > (int64_t(1) << 28)) return fail(h, LBMD_EINVAL, "set_particles: too many particles");
   if (!finite_all(pos, 3 * n) || (vel && !finite_all(vel, 3 * n)))
     return fail(h, LBMD_EINVAL, "set_particles: non-finite input");
@@ -367,6 +536,7 @@ int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double
 
 int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, const double* mass,
                             const double* charge) {
+  if (h) graph_invalidate(h);
   if (!h || ntypes < 1 || ntypes > LBMD_MAX_TYPES || !kappa || !mass)
     return fail(h, LBMD_EINVAL, "set_particle_types: bad arguments");
   for (int t = 0; t < ntypes; ++t)
@@ -385,6 +555,7 @@ int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, 
 }
 
 int lbmd_set_pair_potential(lbmd_handle h, int32_t kind, const double* q) {
+  if (h) graph_invalidate(h);
   if (!h) return LBMD_EINVAL;
   const double half = 0.5 * std::min({h->p.nx, h->p.ny, h->p.nz});
   HIPCHECK(h, hipStreamSynchronize(h->stream));
@@ -434,6 +605,7 @@ int lbmd_set_pair_potential(lbmd_handle h, int32_t kind, const double* q) {
 }
 
 int lbmd_set_bonds(lbmd_handle h, int64_t nb, const int32_t* pairs) {
+  if (h) graph_invalidate(h);
   if (!h || nb < 0 || (nb > 0 && !pairs)) return fail(h, LBMD_EINVAL, "set_bonds: bad arguments");
   std::vector<int32_t> deg(h->np + 1, 0);
   for (int64_t b = 0; b < nb; ++b) {
@@ -465,22 +637,25 @@ int lbmd_set_bonds(lbmd_handle h, int64_t nb, const int32_t* pairs) {
 int lbmd_step(lbmd_handle h, int64_t nsteps) {
   if (!h || nsteps < 0) return fail(h, LBMD_EINVAL, "step: bad arguments");
   if (h->latched) return fail(h, LBMD_ESTATE, "step: a numerical failure is latched");
-  for (int64_t k = 0; k < nsteps; ++k) {
-    const bool parts = h->np > 0;
-    if (parts) {
-      HIPCHECK(h, particles_begin(h));
-      HIPCHECK(h, particles_pairs(h));
+  int64_t k = 0;
+  while (k < nsteps) {
+    // two steps at a time from a captured graph (the ping-pong parity
+    // returns), else one step launched kernel by kernel
+    int64_t done = 1;
+    if (h->use_graph && !h->prof_on && nsteps - k >= 2) {
+      if (!h->gexec[h->cur]) {
+        if (int rc = capture_two_steps(h)) return rc;
+      }
+      HIPCHECK(h, hipGraphLaunch(h->gexec[h->cur], h->stream));
+      done = 2;
     } else {
-      h->red_part_used = 0;
+      if (int rc = enqueue_step(h)) return rc;
+      h->cur = 1 - h->cur;
     }
-    HIPCHECK(h, fluid_pass_a(h));
-    if (parts) HIPCHECK(h, particles_forces(h));
-    HIPCHECK(h, fluid_pass_b(h));
-    if (parts) HIPCHECK(h, particles_end(h));
-    HIPCHECK(h, finalize_step(h));
-    h->cur = 1 - h->cur;
-    h->step += 1;
-    if (h->p.check_every > 0 && h->step % h->p.check_every == 0)
+    const int64_t before = h->step;
+    h->step += done;
+    k += done;
+    if (h->p.check_every > 0 && h->step / h->p.check_every != before / h->p.check_every)
       if (int rc = poll_status(h)) return rc;
   }
   return LBMD_OK;
@@ -556,6 +731,7 @@ int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z, int32_t flags
   h->xcd = flags & LBMD_TILE_XCD ? 1 : 0;
   h->nt = flags & LBMD_TILE_NT ? 1 : 0;
   h->tiling_set = true;
+  graph_invalidate(h);
   return LBMD_OK;
 }
 
@@ -575,6 +751,20 @@ int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t*
   if (enable) h->prof_n = 0;
   h->prof_on = enable != 0;
   return LBMD_OK;
+}
+
+int lbmd_set_graph(lbmd_handle h, int32_t enable) {
+  if (!h) return LBMD_EINVAL;
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  h->use_graph = enable != 0;
+  if (!h->use_graph) graph_invalidate(h);
+  return LBMD_OK;
+}
+
+int lbmd_autotune(lbmd_handle h, int32_t reps, const char* cache_path, int32_t* chosen, double* best_ms) {
+  if (!h || reps < 1) return fail(h, LBMD_EINVAL, "autotune: bad arguments");
+  if (h->latched) return fail(h, LBMD_ESTATE, "autotune: a numerical failure is latched");
+  return autotune(h, reps, cache_path, chosen, best_ms);
 }
 
 }  // extern "C"

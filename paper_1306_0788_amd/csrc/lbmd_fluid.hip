@@ -455,6 +455,7 @@ __global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S
                                                     const uint32_t* __restrict__ mask, arith_t<S>* __restrict__ rec,
                                                     double* __restrict__ red, uint32_t* status, long long* bad) {
   using C = arith_t<S>;
+  load_step(K);
   __shared__ C ring[4][2][TY + 2][66];
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
@@ -568,6 +569,7 @@ __global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __res
                                              const int32_t* __restrict__ nlist, const arith_t<S>* __restrict__ rec,
                                              arith_t<S>* __restrict__ gP, uint32_t* __restrict__ mask) {
   using C = arith_t<S>;
+  load_step(K);
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= *nlist) return;
   const int64_t N = K.N;
@@ -596,6 +598,7 @@ __global__ __launch_bounds__(64 * TY) void k_moments(const S* __restrict__ src_,
                                                       const uint32_t* __restrict__ mask, arith_t<S>* __restrict__ rec,
                                                       double* __restrict__ red, uint32_t* status, long long* bad) {
   using C = arith_t<S>;
+  load_step(K);
   __shared__ C ring[4][2][TY + 2][66];
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
@@ -698,6 +701,7 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
                                                       int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
                                                       arith_t<S>* __restrict__ gP) {
   using C = arith_t<S>;
+  load_step(K);
   __shared__ C ring[4][2][TY + 2][66];
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
@@ -755,7 +759,7 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
 
 // final reductions: fluid partials [nf][5], particle partials [np][3] -> out[8]
 __global__ void k_finalize(const double* __restrict__ rf, int64_t nf, const double* __restrict__ rp, int64_t npb,
-                           double* __restrict__ out, int32_t* nflag) {
+                           double* __restrict__ out, int32_t* nflag, int64_t* step) {
   __shared__ double sh[256];
   for (int q = 0; q < 8; ++q) {
     double s = 0;
@@ -772,7 +776,10 @@ __global__ void k_finalize(const double* __restrict__ rf, int64_t nf, const doub
     if (threadIdx.x == 0) out[q] = sh[0];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *nflag = 0;
+  if (threadIdx.x == 0) {
+    *nflag = 0;
+    *step += 1;
+  }
 }
 
 // ------------------------------------------------------------ launchers
@@ -792,12 +799,12 @@ FluidConsts<arith_t<S>> consts(const lbmd_ctx* h) {
   }
   K.kT = C(h->p.kT);
   K.rho0 = Storage<S>::deviation ? C(h->p.rho0) : C(0);
-  K.srkey = mix32(uint32_t(h->step) ^ mix32(uint32_t(uint64_t(h->step) >> 32) ^ mix32(uint32_t(h->p.seed) ^
-                                                                                   uint32_t(h->p.seed >> 32))));
+  K.srkey = 0;  // set from the device step counter in the kernel
   K.forcing = h->p.forcing;
   K.noise = h->p.kT > 0.0;
   K.seed = h->p.seed;
-  K.step = h->step;
+  K.step = 0;  // likewise
+  K.stepp = h->step_dev;
   K.nt = h->nt;
   return K;
 }
@@ -976,7 +983,7 @@ LBMD_DISPATCH(pass_b)
 
 hipError_t finalize_step(lbmd_ctx* h) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->red_fluid, h->red_fluid_used, h->red_part,
-                     h->red_part_used, h->red_out, h->nflag);
+                     h->red_part_used, h->red_out, h->nflag, h->step_dev);
   return hipGetLastError();
 }
 

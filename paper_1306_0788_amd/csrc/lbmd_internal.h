@@ -177,11 +177,21 @@ struct FluidConsts {
   int forcing;  // LBMD_FORCE_*
   int noise;    // kT > 0
   uint64_t seed;
-  int64_t step;
+  int64_t step;         // filled in the kernel from *stepp (load_step)
+  const int64_t* stepp; // device step counter, advanced by the last kernel of a step
   int nt;  // non-temporal hint on the population stores
   C rho0;  // reference density of deviation storage (0 otherwise)
-  uint32_t srkey;  // per-step key of the stochastic rounding of deviations
+  uint32_t srkey;  // per-step key of the stochastic rounding of deviations (load_step)
 };
+
+// Step index of the launch from the device counter (so that a captured step
+// sequence can be replayed), and the stochastic-rounding key derived from it.
+template <class C>
+__device__ __forceinline__ void load_step(FluidConsts<C>& K) {
+  K.step = *K.stepp;
+  K.srkey = mix32(uint32_t(K.step) ^
+                  mix32(uint32_t(uint64_t(K.step) >> 32) ^ mix32(uint32_t(K.seed) ^ uint32_t(K.seed >> 32))));
+}
 
 }  // namespace lbmd
 
@@ -245,9 +255,14 @@ struct lbmd_ctx {
   double* export_tmp = nullptr;  // staging for host transfers
   size_t export_cap = 0;
 
-  int64_t step = 0;
+  int64_t step = 0;              // steps enqueued (host count)
+  int64_t* step_dev = nullptr;   // steps completed on the device (kernels read it)
   bool latched = false;
   std::string err;
+
+  // replay of captured two-step sequences, one per ping-pong parity
+  bool use_graph = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
 
   // optional event timing of the collide-stream kernel
   bool prof_on = false;

@@ -28,7 +28,8 @@ struct PartArgs {
   int64_t N;
   double gamma, kT;
   uint64_t seed;
-  int64_t step;
+  int64_t step;          // set from *stepp by the kernels that need it
+  const int64_t* stepp;  // device step counter
   ParticleTypes T;
   PairParams pp;
   int ncell[3];
@@ -292,6 +293,7 @@ __global__ __launch_bounds__(256) void k_couple(PartArgs A, const double* __rest
                                                 uint32_t* status, long long* bad) {
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (tid >= A.np) return;
+  A.step = *A.stepp;
   const int64_t p = A.use_cells ? int64_t(perm[tid]) : tid;
   const int t = type[p];
   const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
@@ -334,6 +336,7 @@ __global__ void k_end(PartArgs A, const double* __restrict__ x, double* __restri
                       const int32_t* __restrict__ type, uint32_t* status, long long* bad) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= A.np) return;
+  A.step = *A.stepp;
   const double m = A.T.mass[type[p]];
   bool ok = true;
   for (int a = 0; a < 3; ++a) {
@@ -355,7 +358,8 @@ static PartArgs args(const lbmd_ctx* h) {
   A.gamma = h->p.gamma;
   A.kT = h->p.kT;
   A.seed = h->p.seed;
-  A.step = h->step;
+  A.step = 0;
+  A.stepp = h->step_dev;
   A.T = h->types;
   A.pp = h->pair;
   for (int a = 0; a < 3; ++a) A.ncell[a] = h->ncell[a];

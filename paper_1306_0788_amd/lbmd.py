@@ -23,7 +23,8 @@ MAX_TYPES = 8
 EXPORTS = ["lbmd_create", "lbmd_destroy", "lbmd_set_particles", "lbmd_set_particle_types",
            "lbmd_set_pair_potential", "lbmd_set_bonds", "lbmd_step", "lbmd_sync", "lbmd_get_fields",
            "lbmd_get_particles", "lbmd_set_populations", "lbmd_reductions", "lbmd_get_step",
-           "lbmd_last_error", "lbmd_set_tiling", "lbmd_kernel_timing", "lbmd_organisation"]
+           "lbmd_last_error", "lbmd_set_tiling", "lbmd_kernel_timing", "lbmd_organisation", "lbmd_set_graph",
+           "lbmd_autotune"]
 
 
 class LbmdError(RuntimeError):
@@ -77,6 +78,8 @@ def load():
     L.lbmd_set_tiling.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.lbmd_kernel_timing.argtypes = [H, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64)]
     L.lbmd_organisation.argtypes = [H]
+    L.lbmd_set_graph.argtypes = [H, ctypes.c_int32]
+    L.lbmd_autotune.argtypes = [H, ctypes.c_int32, ctypes.c_char_p, _I32, _D]
     for name in EXPORTS:
         if name not in ("lbmd_get_step", "lbmd_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -228,6 +231,19 @@ class Sim:
         n = ctypes.c_int64()
         self._check(load().lbmd_kernel_timing(self._h, int(enable), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def set_graph(self, enable=True):
+        """Advance steps two at a time by replaying captured HIP graphs."""
+        self._check(load().lbmd_set_graph(self._h, int(enable)))
+
+    def autotune(self, reps=3, cache_path=None):
+        """Time every candidate tiling of the fluid passes on the current state
+        (not advanced) and keep the fastest.  Returns (tile_y, tile_z, flags, ms)."""
+        ch = np.zeros(3, dtype=np.int32)
+        ms = ctypes.c_double()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(load().lbmd_autotune(self._h, reps, path, ch.ctypes.data_as(_I32), ctypes.byref(ms)))
+        return int(ch[0]), int(ch[1]), int(ch[2]), ms.value
 
     def organisation(self):
         """KERNEL_FUSED or KERNEL_TWOPASS: the organisation of the next step."""
