@@ -220,12 +220,15 @@ int enqueue_step(lbmd_ctx* h) {
   const bool parts = h->np > 0;
   if (parts) {
     HIPCHECK(h, particles_begin(h));
-    HIPCHECK(h, particles_pairs(h));
+    HIPCHECK(h, particles_mark_sorted(h));
   } else {
     h->red_part_used = 0;
   }
   HIPCHECK(h, fluid_pass_a(h));
-  if (parts) HIPCHECK(h, particles_forces(h));
+  if (parts) {
+    HIPCHECK(h, particles_pairs(h));
+    HIPCHECK(h, particles_forces(h));
+  }
   HIPCHECK(h, fluid_pass_b(h));
   if (parts) HIPCHECK(h, particles_end(h));
   HIPCHECK(h, finalize_step(h));

@@ -864,18 +864,28 @@ struct Launch {
   int tiles_x, tz, ty;
   int64_t nblk;
 };
-// Tiling actually launched: the caller's (lbmd_set_tiling), else the
-// measured defaults on MI355X at 256^3: 4 rows x 16 planes for the fused
-// kernel (populations held in registers), 16 rows x 64 planes in XCD order
-// for the two-pass kernels.  Rows never exceed the lattice height.
+// Tiling actually launched: the caller's (lbmd_set_tiling or
+// lbmd_autotune), else defaults from measurements on MI355X: the fused
+// kernel with 4 rows and its populations held in registers, the two-pass
+// kernels with 8 rows in XCD order; the z chunk is chosen so that a launch
+// has about 256 blocks (16 and 128 planes at 256^3, the measured optima),
+// within [2, 16] planes for the fused kernel and [4, 128] for the two-pass
+// kernels.  Rows never exceed the lattice height.
+static int pow2_floor(int64_t v) {
+  int p = 1;
+  while (int64_t(p) * 2 <= v) p *= 2;
+  return p;
+}
 static Launch tiles(lbmd_ctx* h) {
   if (!h->tiling_set) {
     const bool fused = organisation_of(h) == LBMD_KERNEL_FUSED;
-    const int want = fused ? 4 : 16;
+    const int want = fused ? 4 : 8;
     int ty = 2;
     while (ty < want && ty * 2 <= h->p.ny) ty *= 2;
+    const int64_t cols = int64_t((h->p.nx + 63) / 64) * ((h->p.ny + ty - 1) / ty);
+    const int tz = pow2_floor(std::max<int64_t>(1, cols * h->p.nz / 256));
     h->tile_y = ty;
-    h->tile_z = fused ? 16 : 64;
+    h->tile_z = fused ? std::min(16, std::max(2, tz)) : std::min(128, std::max(4, tz));
     h->hold = 1;
     h->xcd = fused ? 0 : 1;
   }

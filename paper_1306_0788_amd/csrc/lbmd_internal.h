@@ -284,6 +284,7 @@ hipError_t finalize_step(lbmd_ctx* h);  // reductions, counters
 int organisation_of(const lbmd_ctx* h);  // LBMD_KERNEL_FUSED or _TWOPASS this step
 // launchers (lbmd_particles.hip)
 hipError_t particles_begin(lbmd_ctx* h);  // reduction terms, half kick, drift, flags, cells
+hipError_t particles_mark_sorted(lbmd_ctx* h);  // cell sort done (event for the side stream)
 hipError_t particles_pairs(lbmd_ctx* h);  // conservative forces (side stream)
 hipError_t particles_forces(lbmd_ctx* h); // coupling forces, total force, spread
 hipError_t particles_end(lbmd_ctx* h);    // second half kick

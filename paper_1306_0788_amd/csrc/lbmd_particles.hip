@@ -392,12 +392,20 @@ bool has_conservative(const lbmd_ctx* h) {
   return h->pair.wca_on || h->pair.dh_on || (h->pair.fene_on && h->bond_start);
 }
 
-// conservative forces on the side stream, ordered after the kick/drift/cell
-// sort on the main stream; the main stream waits for them before coupling
+// Conservative forces on the side stream, ordered after the kick/drift/cell
+// sort on the main stream (particles_mark_sorted records that point); the
+// main stream waits for them before coupling.  The density pass is enqueued
+// between the two calls, so it is dispatched first and gets the whole chip
+// in its first wave of blocks, with the pair forces filling in beside it
+// (also in a captured graph, whose nodes follow the enqueue order).
+hipError_t particles_mark_sorted(lbmd_ctx* h) {
+  if (!has_conservative(h)) return hipSuccess;
+  return hipEventRecord(h->ev_sorted, h->stream);
+}
+
 hipError_t particles_pairs(lbmd_ctx* h) {
   if (!has_conservative(h)) return hipSuccess;
   PartArgs A = args(h);
-  if (hipError_t e = hipEventRecord(h->ev_sorted, h->stream)) return e;
   if (hipError_t e = hipStreamWaitEvent(h->side, h->ev_sorted, 0)) return e;
   hipLaunchKernelGGL(k_pairs, dim3((h->np + 255) / 256), dim3(256), 0, h->side, A, h->x, h->type, h->cell_start,
                      h->cell_perm, h->cell_of, h->bond_start, h->bond_nbr, h->Fcons);

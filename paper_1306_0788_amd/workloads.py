@@ -27,16 +27,18 @@ WCA_CUT = 2.0 ** (1.0 / 6.0)
 # Parameter sets.  "shape" = (nx, ny, nz); G is the 2x2 coupling matrix.
 # "onset" is the first step at which a density reaches zero when the set-up
 # starts from its seeded uniform mixture (G_AB = 1.8 is 1.8 times the spinodal
-# coupling of the rho = 1 mixture; the decomposition overshoots the
-# coexistence densities and drains the minority component), as measured for
-# these seeds; None where the run length stays below it.
+# coupling of the rho = 1 mixture with the paper's forcing; with the velocity
+# shift the spinodal is at G rho = (tau - 1/2)/tau, so G_AB = 1.6 is 3.2 times
+# it; the decomposition overshoots the coexistence densities and drains the
+# minority component), as measured for these seeds; None where the run length
+# stays below it.
 WORKLOADS = {
     # 32^3 FP64, velocity-shift forcing, 64 free particles, friction only.
     "c1": dict(shape=(32, 32, 32), precision="fp64", forcing="shift", tau=(1.0, 1.0),
                G=((0.0, 1.6), (1.6, 0.0)), gamma=0.5, kT=0.0, seed=1,
                kappa=((0.0, 0.0),), mass=(1.0,), charge=(0.0,),
                particles=dict(kind="free", n=64, min_dist=0.0), wca=None, fene=None, dh=None,
-               steps=100, onset=None),
+               steps=100, onset=35),
     # 128^3 FP32 spinodal decomposition with 20,000 solvated WCA particles.
     "c2": dict(shape=(128, 128, 128), precision="fp32", forcing="paper", tau=(1.0, 1.0),
                G=((0.0, 1.8), (1.8, 0.0)), gamma=1.0, kT=0.0, seed=2,

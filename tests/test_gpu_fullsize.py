@@ -127,7 +127,7 @@ def test_instability_onset_matches_oracle():
     assert abs(bad_g - bad_o) <= 1
 
 
-@pytest.mark.parametrize("name", ["c2", "c2_256", "c3"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c2_256", "c3"])
 def test_recorded_onset(name):
     """The step at which each G_AB = 1.8 workload first drives a density to
     zero, in the bench configuration, is the one recorded with the workload
