@@ -259,6 +259,55 @@ int lbmd_set_graph(lbmd_handle h, int32_t enable);
    LBMD_ESTATE (failure latched), LBMD_EDEVICE. */
 int lbmd_autotune(lbmd_handle h, int32_t reps, const char* cache_path, int32_t* chosen, double* best_ms);
 
+/* ---- multi-lattice batches (serving many independent simulations) ----
+
+   A batch advances every attached handle by one launch sequence per step:
+   six kernels (particle half kick and drift, fused density + collision +
+   streaming pass, coupling forces and spread, re-collision of the touched
+   nodes, second half kick, FP64 sums) whose blocks walk the lattice tiles,
+   particle blocks and touched-node blocks of all attached jobs together, so
+   jobs of uneven size share the device; the sequence is captured once in a
+   HIP graph and replayed, and jobs join and leave by rewriting the device
+   job table.  Each job stops advancing at its own target step or at its own
+   numerical failure, without affecting the others; its results are those
+   of lbmd_step with the fused organisation (bit for bit without particles;
+   with particles up to the order of the float additions of the spread).
+   Jobs must be FP32, use LBMD_FORCE_PAPER, have no pair potentials or bonds
+   and all have kT > 0 or all kT = 0 (the batch's noise setting). */
+typedef struct lbmd_batch_s* lbmd_batch;
+
+/* Create a batch of at most max_jobs slots (1..4096) on the current device.
+   noise: 1 for jobs with kT > 0, 0 for deterministic jobs.  hip_stream as
+   for lbmd_create.  Errors: LBMD_EINVAL, LBMD_ENOMEM, LBMD_EDEVICE. */
+int lbmd_batch_create(int32_t max_jobs, int32_t noise, void* hip_stream, lbmd_batch* out);
+
+/* Detach every job (their handles stay valid) and free the batch. */
+int lbmd_batch_destroy(lbmd_batch b);
+
+/* Attach handle h to a free slot (*slot receives it); the batch will advance
+   it nsteps steps from its current step.  While attached, calls on h other
+   than lbmd_last_error return LBMD_ESTATE.  Errors: LBMD_EINVAL (the job
+   does not meet the batch's conditions), LBMD_ESTATE (no free slot, h in a
+   batch or latched), LBMD_EDEVICE. */
+int lbmd_batch_attach(lbmd_batch b, lbmd_handle h, int64_t nsteps, int32_t* slot);
+
+/* Detach the job in slot (waits for the batch's stream); its handle resumes
+   at the step the batch reached.  Errors: LBMD_EINVAL, LBMD_EDEVICE. */
+int lbmd_batch_detach(lbmd_batch b, int32_t slot);
+
+/* Enqueue nsteps batch steps (jobs past their target or failed stay put).
+   Does not wait.  Errors: LBMD_EINVAL, LBMD_EDEVICE. */
+int lbmd_batch_step(lbmd_batch b, int64_t nsteps);
+
+/* Wait for the batch's stream and report, per slot (arrays of max_jobs):
+   steps[s] = the job's step (-1 if empty), state[s] = 0 empty, 1 running,
+   2 reached its target, 3 numerical failure (details through lbmd_sync on
+   the handle after detaching).  Either array may be NULL. */
+int lbmd_batch_poll(lbmd_batch b, int64_t* steps, int32_t* state);
+
+/* Message of the batch's last error. */
+const char* lbmd_batch_last_error(lbmd_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -448,6 +448,7 @@ int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, 
 
 int lbmd_destroy(lbmd_handle h) {
   if (!h) return LBMD_EINVAL;
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (int b = 0; b < 2; ++b)
     if (h->f[b]) (void)hipFree(h->f[b]);
@@ -480,6 +481,7 @@ int lbmd_destroy(lbmd_handle h) {
 
 int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double* vel, const int32_t* type) {
   if (!h || n < 0 || (n > 0 && !pos)) return fail(h, LBMD_EINVAL, "set_particles: bad arguments");
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   graph_invalidate(h);
   if (n > (int64_t(1) << 28)) return fail(h, LBMD_EINVAL, "set_particles: too many particles");
   if (!finite_all(pos, 3 * n) || (vel && !finite_all(vel, 3 * n)))
@@ -539,6 +541,7 @@ int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double
 
 int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, const double* mass,
                             const double* charge) {
+  if (h && h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (h) graph_invalidate(h);
   if (!h || ntypes < 1 || ntypes > LBMD_MAX_TYPES || !kappa || !mass)
     return fail(h, LBMD_EINVAL, "set_particle_types: bad arguments");
@@ -558,6 +561,7 @@ int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, 
 }
 
 int lbmd_set_pair_potential(lbmd_handle h, int32_t kind, const double* q) {
+  if (h && h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (h) graph_invalidate(h);
   if (!h) return LBMD_EINVAL;
   const double half = 0.5 * std::min({h->p.nx, h->p.ny, h->p.nz});
@@ -608,6 +612,7 @@ int lbmd_set_pair_potential(lbmd_handle h, int32_t kind, const double* q) {
 }
 
 int lbmd_set_bonds(lbmd_handle h, int64_t nb, const int32_t* pairs) {
+  if (h && h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (h) graph_invalidate(h);
   if (!h || nb < 0 || (nb > 0 && !pairs)) return fail(h, LBMD_EINVAL, "set_bonds: bad arguments");
   std::vector<int32_t> deg(h->np + 1, 0);
@@ -639,6 +644,7 @@ int lbmd_set_bonds(lbmd_handle h, int64_t nb, const int32_t* pairs) {
 
 int lbmd_step(lbmd_handle h, int64_t nsteps) {
   if (!h || nsteps < 0) return fail(h, LBMD_EINVAL, "step: bad arguments");
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (h->latched) return fail(h, LBMD_ESTATE, "step: a numerical failure is latched");
   int64_t k = 0;
   while (k < nsteps) {
@@ -666,6 +672,7 @@ int lbmd_step(lbmd_handle h, int64_t nsteps) {
 
 int lbmd_sync(lbmd_handle h) {
   if (!h) return LBMD_EINVAL;
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   return poll_status(h);
 }
@@ -673,6 +680,7 @@ int lbmd_sync(lbmd_handle h) {
 int lbmd_get_fields(lbmd_handle h, uint32_t mask, double* out, int32_t out_is_device) {
   if (!h || !out || mask == 0 || (mask & ~(LBMD_RHO | LBMD_U | LBMD_POP)))
     return fail(h, LBMD_EINVAL, "get_fields: bad arguments");
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   size_t n = 0;
   if (mask & LBMD_RHO) n += 2 * h->N;
   if (mask & LBMD_U) n += 3 * h->N;
@@ -692,6 +700,7 @@ int lbmd_get_fields(lbmd_handle h, uint32_t mask, double* out, int32_t out_is_de
 
 int lbmd_get_particles(lbmd_handle h, double* pos, double* vel, double* force, double* fcoup) {
   if (!h) return LBMD_EINVAL;
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   const size_t b = 3 * h->np * sizeof(double);
   if (h->np > 0) {
@@ -706,6 +715,7 @@ int lbmd_get_particles(lbmd_handle h, double* pos, double* vel, double* force, d
 
 int lbmd_set_populations(lbmd_handle h, const double* pop) {
   if (!h || !pop) return fail(h, LBMD_EINVAL, "set_populations: NULL");
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (int rc = ensure_staging(h, 38 * h->N)) return rc;
   HIPCHECK(h, hipMemcpyAsync(h->export_tmp, pop, 38 * h->N * sizeof(double), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(h, fluid_import(h, h->export_tmp));
@@ -715,6 +725,7 @@ int lbmd_set_populations(lbmd_handle h, const double* pop) {
 
 int lbmd_reductions(lbmd_handle h, double* out, int64_t* step_out) {
   if (!h || !out) return LBMD_EINVAL;
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   HIPCHECK(h, hipMemcpyAsync(out, h->red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   if (step_out) *step_out = h->step - 1;
@@ -726,6 +737,7 @@ int64_t lbmd_get_step(lbmd_handle h) { return h ? h->step : -1; }
 const char* lbmd_last_error(lbmd_handle h) { return h ? h->err.c_str() : "NULL handle"; }
 
 int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z, int32_t flags) {
+  if (h && h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (!h || !(tile_y == 2 || tile_y == 4 || tile_y == 8 || tile_y == 16) || tile_z < 1 || (flags & ~7))
     return fail(h, LBMD_EINVAL, "set_tiling: tile_y in {2,4,8,16}, tile_z >= 1, flags in 0..7");
   h->tile_y = tile_y;
@@ -758,6 +770,7 @@ int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t*
 
 int lbmd_set_graph(lbmd_handle h, int32_t enable) {
   if (!h) return LBMD_EINVAL;
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   h->use_graph = enable != 0;
   if (!h->use_graph) graph_invalidate(h);
@@ -766,6 +779,7 @@ int lbmd_set_graph(lbmd_handle h, int32_t enable) {
 
 int lbmd_autotune(lbmd_handle h, int32_t reps, const char* cache_path, int32_t* chosen, double* best_ms) {
   if (!h || reps < 1) return fail(h, LBMD_EINVAL, "autotune: bad arguments");
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (h->latched) return fail(h, LBMD_ESTATE, "autotune: a numerical failure is latched");
   return autotune(h, reps, cache_path, chosen, best_ms);
 }

@@ -355,17 +355,17 @@ struct Tile {
   int x0, y0, z0, z1, twv, thv, ringA, nring, x, y, lane, wv;
   bool inside;
   int bid;
-  __device__ Tile(int nx, int ny, int nz, int tz, int tiles_x, int xcd) {
+  // block: this block's index among the nblk blocks of the lattice
+  __device__ Tile(int nx, int ny, int nz, int tz, int tiles_x, int xcd, int block, int nblk) {
     lane = threadIdx.x & 63;
     wv = threadIdx.x >> 6;
     const int nchunk = (nz + tz - 1) / tz;
-    const int nblk = gridDim.x;
     int bx, by, bz;
     if (xcd) {
       // blocks are dealt to the 8 XCDs in turn; renumber so that each XCD
       // runs a contiguous range of tiles ordered x, then y, then z: tiles
       // that share border rows then run together on one L2
-      const int k = blockIdx.x & 7, m = blockIdx.x >> 3;
+      const int k = block & 7, m = block >> 3;
       const int q = nblk >> 3, r = nblk & 7;
       bid = k * q + min(k, r) + m;
       const int tiles_y = (ny + TY - 1) / TY;
@@ -374,7 +374,7 @@ struct Tile {
       bz = bid / (tiles_x * tiles_y);
     } else {
       // consecutive block ids walk the z chunks of one column of tiles
-      bid = blockIdx.x;
+      bid = block;
       bz = bid % nchunk;
       const int bxy = bid / nchunk;
       bx = bxy % tiles_x;
@@ -450,10 +450,10 @@ __device__ __forceinline__ void nsum_ring(const C (&ring)[4][2][TY + 2][66], int
 // every site without particle force, records at touched nodes; k_fix then
 // re-collides the touched nodes.  Best when few nodes are touched.
 template <class S, int TY, int FORCING, bool NOISE, bool HOLD>
-__global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S* __restrict__ dst_,
-                                                    FluidConsts<arith_t<S>> K, int tz, int tiles_x, int xcd,
-                                                    const uint32_t* __restrict__ mask, arith_t<S>* __restrict__ rec,
-                                                    double* __restrict__ red, uint32_t* status, long long* bad) {
+__device__ __forceinline__ void fused_tile(const S* __restrict__ src_, S* __restrict__ dst_, FluidConsts<arith_t<S>> K,
+                                           int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
+                                           arith_t<S>* __restrict__ rec, double* __restrict__ red, uint32_t* status,
+                                           long long* bad, int block, int nblk) {
   using C = arith_t<S>;
   load_step(K);
   __shared__ C ring[4][2][TY + 2][66];
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S
   const int64_t N = K.N;
   const int64_t plane = int64_t(nx) * ny;
   const Pops<S> src = make_pops(src_, N, K.rho0), dst = make_pops<S>(dst_, N, K.rho0, K.srkey);
-  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
+  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd, block, nblk);
   const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
 
   C cur[2][19], nxt[2][19];
@@ -561,16 +561,24 @@ __global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S
   block_sum5<TY>(acc, red + 5 * int64_t(T.bid));
 }
 
+template <class S, int TY, int FORCING, bool NOISE, bool HOLD>
+__global__ __launch_bounds__(64 * TY) void k_fused(const S* __restrict__ src_, S* __restrict__ dst_,
+                                                    FluidConsts<arith_t<S>> K, int tz, int tiles_x, int xcd,
+                                                    const uint32_t* __restrict__ mask, arith_t<S>* __restrict__ rec,
+                                                    double* __restrict__ red, uint32_t* status, long long* bad) {
+  fused_tile<S, TY, FORCING, NOISE, HOLD>(src_, dst_, K, tz, tiles_x, xcd, mask, rec, red, status, bad, blockIdx.x,
+                                          gridDim.x);
+}
+
 // re-collide the touched nodes with the spread particle force; clears the
 // node force and the mask as it goes
 template <class S, int FORCING, bool NOISE>
-__global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __restrict__ dst,
-                                             FluidConsts<arith_t<S>> K, const int32_t* __restrict__ list,
-                                             const int32_t* __restrict__ nlist, const arith_t<S>* __restrict__ rec,
-                                             arith_t<S>* __restrict__ gP, uint32_t* __restrict__ mask) {
+__device__ __forceinline__ void fix_node(const S* __restrict__ src, S* __restrict__ dst, FluidConsts<arith_t<S>> K,
+                                         const int32_t* __restrict__ list, const int32_t* __restrict__ nlist,
+                                         const arith_t<S>* __restrict__ rec, arith_t<S>* __restrict__ gP,
+                                         uint32_t* __restrict__ mask, int64_t t) {
   using C = arith_t<S>;
   load_step(K);
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= *nlist) return;
   const int64_t N = K.N;
   const int64_t s = list[t];
@@ -589,6 +597,14 @@ __global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __res
   store<S, C>(make_pops<S>(dst, N, K.rho0, K.srkey), uint32_t(s), f);
 }
 
+template <class S, int FORCING, bool NOISE>
+__global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __restrict__ dst, FluidConsts<arith_t<S>> K,
+                                             const int32_t* __restrict__ list, const int32_t* __restrict__ nlist,
+                                             const arith_t<S>* __restrict__ rec, arith_t<S>* __restrict__ gP,
+                                             uint32_t* __restrict__ mask) {
+  fix_node<S, FORCING, NOISE>(src, dst, K, list, nlist, rec, gP, mask, int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
 // ------------------------------------------------------------ split path
 // Pass P: density field, conservation sums, status, and the records at the
 // touched nodes (neighbour sums from the density ring, u_c).  No collision.
@@ -604,7 +620,7 @@ __global__ __launch_bounds__(64 * TY) void k_moments(const S* __restrict__ src_,
   const int64_t N = K.N;
   const int64_t plane = int64_t(nx) * ny;
   const Pops<S> src = make_pops(src_, N, K.rho0);
-  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
+  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd, blockIdx.x, gridDim.x);
   const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
   double acc[5] = {0, 0, 0, 0, 0};
   C jn[3] = {0, 0, 0}, jc[3] = {0, 0, 0};  // raw momentum of the next / current plane
@@ -707,7 +723,7 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
   const int64_t N = K.N;
   const int64_t plane = int64_t(nx) * ny;
   const Pops<S> src = make_pops(src_, N, K.rho0), dst = make_pops<S>(dst_, N, K.rho0, K.srkey);
-  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd);
+  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd, blockIdx.x, gridDim.x);
   const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
 
   auto load_interior = [&](int zp_raw, int slot) {
@@ -758,8 +774,8 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
 }
 
 // final reductions: fluid partials [nf][5], particle partials [np][3] -> out[8]
-__global__ void k_finalize(const double* __restrict__ rf, int64_t nf, const double* __restrict__ rp, int64_t npb,
-                           double* __restrict__ out, int32_t* nflag, int64_t* step) {
+__device__ __forceinline__ void finalize_sums(const double* __restrict__ rf, int64_t nf, const double* __restrict__ rp,
+                                              int64_t npb, double* __restrict__ out, int32_t* nflag, int64_t* step) {
   __shared__ double sh[256];
   for (int q = 0; q < 8; ++q) {
     double s = 0;
@@ -780,6 +796,10 @@ __global__ void k_finalize(const double* __restrict__ rf, int64_t nf, const doub
     *nflag = 0;
     *step += 1;
   }
+}
+__global__ void k_finalize(const double* __restrict__ rf, int64_t nf, const double* __restrict__ rp, int64_t npb,
+                           double* __restrict__ out, int32_t* nflag, int64_t* step) {
+  finalize_sums(rf, nf, rp, npb, out, nflag, step);
 }
 
 // ------------------------------------------------------------ launchers
@@ -998,5 +1018,132 @@ hipError_t finalize_step(lbmd_ctx* h) {
 }
 
 int organisation_of(const lbmd_ctx* h) { return organisation(h); }
+
+// ------------------------------------------------------------ batches
+// Index of the job whose range [begin, next begin) holds unit u (jobs in
+// order of increasing begin; a job with no units shares its begin with the
+// next one, and the last such job is the one that owns u).
+template <int64_t BatchJob::*BEGIN>
+__device__ __forceinline__ int batch_job_of(const BatchJob* __restrict__ jobs, int nj, int64_t u) {
+  int lo = 0, hi = nj - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].*BEGIN <= u)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ bool batch_active(const BatchJob& J) { return *J.step < J.target && *J.status == 0u; }
+
+// Fluid pass of every job: each block walks lattice tiles of the flattened
+// tile range (the global tile queue), one z-march per tile.
+template <bool NOISE>
+__global__ __launch_bounds__(64 * BATCH_TY) void k_fused_batch(const BatchJob* __restrict__ jobs,
+                                                                const BatchHeader* __restrict__ hdr) {
+  __shared__ int act;
+  const int nj = hdr->njobs;
+  const int64_t total = hdr->ntiles;
+  for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const BatchJob& J = jobs[batch_job_of<&BatchJob::tile_begin>(jobs, nj, u)];
+    if (threadIdx.x == 0) act = batch_active(J) ? 1 : 0;  // the status word may change meanwhile
+    __syncthreads();
+    const bool a = act != 0;
+    __syncthreads();
+    if (a) {
+      const int par = int(*J.step & 1);
+      fused_tile<float, BATCH_TY, LBMD_FORCE_PAPER, NOISE, true>(J.f[par], const_cast<float*>(J.f[1 - par]), J.K,
+                                                                 J.tz, J.tiles_x, 0, J.mask, J.rec, J.red_fluid,
+                                                                 J.status, J.bad, int(u - J.tile_begin), J.nblk);
+    }
+    __syncthreads();  // the LDS ring is reused by the next tile
+  }
+}
+
+// Re-collision of the touched nodes of every job.
+template <bool NOISE>
+__global__ __launch_bounds__(256) void k_fix_batch(const BatchJob* __restrict__ jobs,
+                                                   const BatchHeader* __restrict__ hdr) {
+  const int nj = hdr->njobs;
+  const int64_t total = hdr->nfixblk;
+  for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const BatchJob& J = jobs[batch_job_of<&BatchJob::fix_begin>(jobs, nj, u)];
+    if (!batch_active(J)) continue;
+    const int par = int(*J.step & 1);
+    fix_node<float, LBMD_FORCE_PAPER, NOISE>(J.f[par], const_cast<float*>(J.f[1 - par]), J.K, J.flag_list, J.nflag,
+                                             J.rec, J.gP, J.mask, (u - J.fix_begin) * 256 + threadIdx.x);
+  }
+}
+
+// Conservation sums and step counter of every job (one block per job slot).
+__global__ void k_finalize_batch(const BatchJob* __restrict__ jobs, const BatchHeader* __restrict__ hdr) {
+  __shared__ int act;
+  const int j = blockIdx.x;
+  if (j >= hdr->njobs) return;
+  const BatchJob& J = jobs[j];
+  if (threadIdx.x == 0) act = batch_active(J) ? 1 : 0;
+  __syncthreads();
+  if (!act) return;
+  finalize_sums(J.red_fluid, J.nblk, J.red_part, J.npblk, J.red_out, J.nflag, J.step);
+}
+
+constexpr int BATCH_FLUID_GRID = 2048, BATCH_FIX_GRID = 1024;
+
+hipError_t batch_fluid_pass(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, bool noise) {
+  if (noise)
+    hipLaunchKernelGGL(k_fused_batch<true>, dim3(BATCH_FLUID_GRID), dim3(64 * BATCH_TY), 0, st, jobs, hdr);
+  else
+    hipLaunchKernelGGL(k_fused_batch<false>, dim3(BATCH_FLUID_GRID), dim3(64 * BATCH_TY), 0, st, jobs, hdr);
+  return hipGetLastError();
+}
+hipError_t batch_fluid_fix(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, bool noise) {
+  if (noise)
+    hipLaunchKernelGGL(k_fix_batch<true>, dim3(BATCH_FIX_GRID), dim3(256), 0, st, jobs, hdr);
+  else
+    hipLaunchKernelGGL(k_fix_batch<false>, dim3(BATCH_FIX_GRID), dim3(256), 0, st, jobs, hdr);
+  return hipGetLastError();
+}
+hipError_t batch_finalize(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, int max_jobs) {
+  hipLaunchKernelGGL(k_finalize_batch, dim3(max_jobs), dim3(256), 0, st, jobs, hdr);
+  return hipGetLastError();
+}
+
+// (step, status) of every job of the table, for the host's poll
+__global__ void k_gather_batch(const BatchJob* __restrict__ jobs, const BatchHeader* __restrict__ hdr,
+                               int64_t* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= hdr->njobs) return;
+  out[2 * j] = *jobs[j].step;
+  out[2 * j + 1] = int64_t(*jobs[j].status);
+}
+hipError_t batch_gather(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, int max_jobs, int64_t* out) {
+  hipLaunchKernelGGL(k_gather_batch, dim3((max_jobs + 63) / 64), dim3(64), 0, st, jobs, hdr, out);
+  return hipGetLastError();
+}
+
+// The job's constants, buffers and fused tiling (4 rows per tile, the z
+// chunk of the default rule).
+void batch_fill_fluid(const lbmd_ctx* h, BatchJob& J) {
+  J.K = consts<float>(h);
+  J.step = h->step_dev;
+  J.f[0] = (const float*)h->f[0];
+  J.f[1] = (const float*)h->f[1];
+  J.mask = h->np > 0 ? h->mask : nullptr;
+  J.rec = (float*)h->rec;
+  J.gP = (float*)h->gP;
+  J.red_fluid = h->red_fluid;
+  J.red_out = h->red_out;
+  J.status = h->status;
+  J.bad = h->bad_step;
+  J.nflag = h->nflag;
+  J.flag_list = h->flag_list;
+  J.tiles_x = (h->p.nx + 63) / 64;
+  const int64_t tiles_y = (h->p.ny + BATCH_TY - 1) / BATCH_TY;
+  const int tz = pow2_floor(std::max<int64_t>(1, J.tiles_x * tiles_y * h->p.nz / 256));
+  J.tz = std::min(16, std::max(2, std::min(tz, h->p.nz)));
+  J.nblk = int(J.tiles_x * tiles_y * ((h->p.nz + J.tz - 1) / J.tz));
+  J.nfixblk = h->np > 0 ? (h->flag_cap + 255) / 256 : 0;
+}
 
 }  // namespace lbmd

@@ -165,6 +165,22 @@ struct PairParams {
   double fene_k, fene_R0;
 };
 
+// Scalar parameters of the particle kernels, passed by value.
+struct PartArgs {
+  int64_t np;
+  int nx, ny, nz;
+  int64_t N;
+  double gamma, kT;
+  uint64_t seed;
+  int64_t step;          // set from *stepp by the kernels that need it
+  const int64_t* stepp;  // device step counter
+  ParticleTypes T;
+  PairParams pp;
+  int ncell[3];
+  int use_cells;
+  int build_list;  // append touched nodes to the compact list (fused organisation)
+};
+
 // Scalar parameters of one fluid step, passed by value to the kernels.
 template <class C>
 struct FluidConsts {
@@ -194,6 +210,59 @@ __device__ __forceinline__ void load_step(FluidConsts<C>& K) {
 }
 
 }  // namespace lbmd
+
+namespace lbmd {
+// One job of a multi-lattice batch (FP32 populations, the paper's forcing,
+// fused organisation).  The batch kernels walk the flattened work of all
+// jobs: lattice tiles, blocks of 256 particles and blocks of 256 entries of
+// the touched-node list, each job owning a contiguous range.  A job advances
+// while its step counter is below its target and its status word is clear;
+// the current populations are f[step & 1].
+struct BatchJob {
+  FluidConsts<float> K;  // K.stepp = step
+  int64_t* step;
+  int64_t target;
+  const float* f[2];
+  uint32_t* mask;  // nullptr without particles
+  float* rec;
+  float* gP;
+  double* red_fluid;
+  double* red_part;
+  double* red_out;
+  uint32_t* status;
+  long long* bad;
+  int32_t* flag_list;
+  int32_t* nflag;
+  int tiles_x, tz, nblk;  // fused tiling, 4 rows per tile
+  PartArgs A;             // A.stepp = step
+  double* x;
+  double* v;
+  double* F;
+  double* Fc;
+  int32_t* type;
+  int64_t npblk, nfixblk;                     // particle and node-list blocks
+  int64_t tile_begin, pblk_begin, fix_begin;  // offsets in the flattened work
+};
+struct BatchHeader {
+  int32_t njobs;
+  int32_t pad;
+  int64_t ntiles, npblk, nfixblk;
+};
+constexpr int BATCH_TY = 4;
+// launchers (lbmd_fluid.hip / lbmd_particles.hip); grids are fixed so that a
+// captured step serves any composition of the job table
+hipError_t batch_fluid_pass(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, bool noise);
+hipError_t batch_fluid_fix(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, bool noise);
+hipError_t batch_finalize(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, int max_jobs);
+hipError_t batch_particles_begin(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr);
+hipError_t batch_particles_couple(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr);
+hipError_t batch_particles_end(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr);
+hipError_t batch_gather(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, int max_jobs, int64_t* out);
+void batch_fill_fluid(const lbmd_ctx* h, BatchJob& J);      // K, buffers, tiling
+void batch_fill_particles(const lbmd_ctx* h, BatchJob& J);  // A, particle buffers
+}  // namespace lbmd
+
+struct lbmd_batch_s;
 
 struct lbmd_ctx {
   lbmd_params p;
@@ -259,6 +328,8 @@ struct lbmd_ctx {
   int64_t* step_dev = nullptr;   // steps completed on the device (kernels read it)
   bool latched = false;
   std::string err;
+
+  lbmd_batch_s* batch = nullptr;  // attached to a multi-lattice batch
 
   // replay of captured two-step sequences, one per ping-pong parity
   bool use_graph = false;

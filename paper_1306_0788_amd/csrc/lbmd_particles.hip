@@ -22,20 +22,6 @@
 
 namespace lbmd {
 
-struct PartArgs {
-  int64_t np;
-  int nx, ny, nz;
-  int64_t N;
-  double gamma, kT;
-  uint64_t seed;
-  int64_t step;          // set from *stepp by the kernels that need it
-  const int64_t* stepp;  // device step counter
-  ParticleTypes T;
-  PairParams pp;
-  int ncell[3];
-  int use_cells;
-  int build_list;  // append touched nodes to the compact list (fused organisation)
-};
 
 __device__ __forceinline__ double wrapd(double x, double L) {
   x -= L * floor(x / L);
@@ -82,14 +68,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_begin(PartArgs A, double* __restrict__ x, double* __restrict__ v,
-                                               const double* __restrict__ F, const double* __restrict__ Fc,
-                                               const int32_t* __restrict__ type, uint32_t* __restrict__ mask,
-                                               int32_t* __restrict__ list, int32_t* __restrict__ nlist,
-                                               int32_t* __restrict__ cell_count, int32_t* __restrict__ cell_of,
-                                               int32_t* __restrict__ rank_of, double* __restrict__ red) {
+// one block of 256 particles (block index blk within the lattice's particles)
+__device__ __forceinline__ void begin_block(const PartArgs& A, double* __restrict__ x, double* __restrict__ v,
+                                            const double* __restrict__ F, const double* __restrict__ Fc,
+                                            const int32_t* __restrict__ type, uint32_t* __restrict__ mask,
+                                            int32_t* __restrict__ list, int32_t* __restrict__ nlist,
+                                            int32_t* __restrict__ cell_count, int32_t* __restrict__ cell_of,
+                                            int32_t* __restrict__ rank_of, double* __restrict__ red, int64_t blk) {
   __shared__ double part[4][3];
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t p = blk * 256 + threadIdx.x;
   const bool valid = p < A.np;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double mom[3] = {0, 0, 0};
@@ -149,8 +136,17 @@ __global__ __launch_bounds__(256) void k_begin(PartArgs A, double* __restrict__ 
   if (lane == 0)
     for (int a = 0; a < 3; ++a) part[wv][a] = mom[a];
   __syncthreads();
-  if (threadIdx.x < 3) red[3 * blockIdx.x + threadIdx.x] = part[0][threadIdx.x] + part[1][threadIdx.x] +
-                                                             part[2][threadIdx.x] + part[3][threadIdx.x];
+  if (threadIdx.x < 3) red[3 * blk + threadIdx.x] = part[0][threadIdx.x] + part[1][threadIdx.x] +
+                                                   part[2][threadIdx.x] + part[3][threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_begin(PartArgs A, double* __restrict__ x, double* __restrict__ v,
+                                               const double* __restrict__ F, const double* __restrict__ Fc,
+                                               const int32_t* __restrict__ type, uint32_t* __restrict__ mask,
+                                               int32_t* __restrict__ list, int32_t* __restrict__ nlist,
+                                               int32_t* __restrict__ cell_count, int32_t* __restrict__ cell_of,
+                                               int32_t* __restrict__ rank_of, double* __restrict__ red) {
+  begin_block(A, x, v, F, Fc, type, mask, list, nlist, cell_count, cell_of, rank_of, red, blockIdx.x);
 }
 
 // exclusive scan of cell counts: per-1024 block, then block totals, then add
@@ -285,13 +281,12 @@ __global__ __launch_bounds__(256) void k_pairs(PartArgs A, const double* __restr
 // solvation_kappa) + random force; total force F = coupling + conservative;
 // the opposite coupling force spread onto the 8 nodes.
 template <class C>
-__global__ __launch_bounds__(256) void k_couple(PartArgs A, const double* __restrict__ x,
-                                                const double* __restrict__ v, double* __restrict__ F,
-                                                double* __restrict__ Fc, const double* __restrict__ Fcons,
-                                                const int32_t* __restrict__ type, const C* __restrict__ rec,
-                                                C* __restrict__ gP, const int32_t* __restrict__ perm,
-                                                uint32_t* status, long long* bad) {
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict__ x, const double* __restrict__ v,
+                                           double* __restrict__ F, double* __restrict__ Fc,
+                                           const double* __restrict__ Fcons, const int32_t* __restrict__ type,
+                                           const C* __restrict__ rec, C* __restrict__ gP,
+                                           const int32_t* __restrict__ perm, uint32_t* status, long long* bad,
+                                           int64_t tid) {
   if (tid >= A.np) return;
   A.step = *A.stepp;
   const int64_t p = A.use_cells ? int64_t(perm[tid]) : tid;
@@ -332,9 +327,19 @@ __global__ __launch_bounds__(256) void k_couple(PartArgs A, const double* __rest
     for (int a = 0; a < 3; ++a) atomicAdd(&gP[node[k] * 4 + a], C(-W[k] * fc[a]));
 }
 
-__global__ void k_end(PartArgs A, const double* __restrict__ x, double* __restrict__ v, const double* __restrict__ F,
-                      const int32_t* __restrict__ type, uint32_t* status, long long* bad) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+template <class C>
+__global__ __launch_bounds__(256) void k_couple(PartArgs A, const double* __restrict__ x,
+                                                const double* __restrict__ v, double* __restrict__ F,
+                                                double* __restrict__ Fc, const double* __restrict__ Fcons,
+                                                const int32_t* __restrict__ type, const C* __restrict__ rec,
+                                                C* __restrict__ gP, const int32_t* __restrict__ perm,
+                                                uint32_t* status, long long* bad) {
+  couple_one<C>(A, x, v, F, Fc, Fcons, type, rec, gP, perm, status, bad, int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+__device__ __forceinline__ void end_one(PartArgs A, const double* __restrict__ x, double* __restrict__ v,
+                                        const double* __restrict__ F, const int32_t* __restrict__ type,
+                                        uint32_t* status, long long* bad, int64_t p) {
   if (p >= A.np) return;
   A.step = *A.stepp;
   const double m = A.T.mass[type[p]];
@@ -345,6 +350,11 @@ __global__ void k_end(PartArgs A, const double* __restrict__ x, double* __restri
     ok = ok && isfinite(vn) && isfinite(x[3 * p + a]);
   }
   if (!ok) flag_unstable(status, bad, 2u, A.step);
+}
+
+__global__ void k_end(PartArgs A, const double* __restrict__ x, double* __restrict__ v, const double* __restrict__ F,
+                      const int32_t* __restrict__ type, uint32_t* status, long long* bad) {
+  end_one(A, x, v, F, type, status, bad, int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------ launchers
@@ -434,6 +444,93 @@ hipError_t particles_end(lbmd_ctx* h) {
   hipLaunchKernelGGL(k_end, dim3((h->np + 255) / 256), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->type,
                      h->status, h->bad_step);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batches
+template <int64_t BatchJob::*BEGIN>
+__device__ __forceinline__ int batch_job_of(const BatchJob* __restrict__ jobs, int nj, int64_t u) {
+  int lo = 0, hi = nj - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].*BEGIN <= u)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ bool batch_active(const BatchJob& J) { return *J.step < J.target && *J.status == 0u; }
+
+// Each block walks blocks of 256 particles of the flattened particle range.
+__global__ __launch_bounds__(256) void k_begin_batch(const BatchJob* __restrict__ jobs,
+                                                     const BatchHeader* __restrict__ hdr) {
+  __shared__ int act;
+  const int nj = hdr->njobs;
+  const int64_t total = hdr->npblk;
+  for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const BatchJob& J = jobs[batch_job_of<&BatchJob::pblk_begin>(jobs, nj, u)];
+    if (threadIdx.x == 0) act = batch_active(J) ? 1 : 0;
+    __syncthreads();
+    const bool a = act != 0;
+    __syncthreads();
+    if (a)
+      begin_block(J.A, J.x, J.v, J.F, J.Fc, J.type, J.mask, J.flag_list, J.nflag, nullptr, nullptr, nullptr,
+                  J.red_part, u - J.pblk_begin);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_couple_batch(const BatchJob* __restrict__ jobs,
+                                                      const BatchHeader* __restrict__ hdr) {
+  const int nj = hdr->njobs;
+  const int64_t total = hdr->npblk;
+  for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const BatchJob& J = jobs[batch_job_of<&BatchJob::pblk_begin>(jobs, nj, u)];
+    if (!batch_active(J)) continue;
+    couple_one<float>(J.A, J.x, J.v, J.F, J.Fc, nullptr, J.type, J.rec, J.gP, nullptr, J.status, J.bad,
+                      (u - J.pblk_begin) * 256 + threadIdx.x);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_end_batch(const BatchJob* __restrict__ jobs,
+                                                   const BatchHeader* __restrict__ hdr) {
+  const int nj = hdr->njobs;
+  const int64_t total = hdr->npblk;
+  for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const BatchJob& J = jobs[batch_job_of<&BatchJob::pblk_begin>(jobs, nj, u)];
+    if (!batch_active(J)) continue;
+    end_one(J.A, J.x, J.v, J.F, J.type, J.status, J.bad, (u - J.pblk_begin) * 256 + threadIdx.x);
+  }
+}
+
+constexpr int BATCH_PART_GRID = 1024;
+
+hipError_t batch_particles_begin(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr) {
+  hipLaunchKernelGGL(k_begin_batch, dim3(BATCH_PART_GRID), dim3(256), 0, st, jobs, hdr);
+  return hipGetLastError();
+}
+hipError_t batch_particles_couple(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr) {
+  hipLaunchKernelGGL(k_couple_batch, dim3(BATCH_PART_GRID), dim3(256), 0, st, jobs, hdr);
+  return hipGetLastError();
+}
+hipError_t batch_particles_end(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr) {
+  hipLaunchKernelGGL(k_end_batch, dim3(BATCH_PART_GRID), dim3(256), 0, st, jobs, hdr);
+  return hipGetLastError();
+}
+
+// Particle arguments of a batch job: no pair potentials (no cell list), the
+// touched nodes appended to the compact list for the re-collision.
+void batch_fill_particles(const lbmd_ctx* h, BatchJob& J) {
+  J.A = args(h);
+  J.A.use_cells = 0;
+  J.A.build_list = 1;
+  J.x = h->x;
+  J.v = h->v;
+  J.F = h->F;
+  J.Fc = h->Fc;
+  J.type = h->type;
+  J.red_part = h->red_part;
+  J.npblk = (h->np + 255) / 256;
 }
 
 }  // namespace lbmd

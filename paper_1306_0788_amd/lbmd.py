@@ -24,7 +24,8 @@ EXPORTS = ["lbmd_create", "lbmd_destroy", "lbmd_set_particles", "lbmd_set_partic
            "lbmd_set_pair_potential", "lbmd_set_bonds", "lbmd_step", "lbmd_sync", "lbmd_get_fields",
            "lbmd_get_particles", "lbmd_set_populations", "lbmd_reductions", "lbmd_get_step",
            "lbmd_last_error", "lbmd_set_tiling", "lbmd_kernel_timing", "lbmd_organisation", "lbmd_set_graph",
-           "lbmd_autotune"]
+           "lbmd_autotune", "lbmd_batch_create", "lbmd_batch_destroy", "lbmd_batch_attach", "lbmd_batch_detach",
+           "lbmd_batch_step", "lbmd_batch_poll", "lbmd_batch_last_error"]
 
 
 class LbmdError(RuntimeError):
@@ -80,8 +81,16 @@ def load():
     L.lbmd_organisation.argtypes = [H]
     L.lbmd_set_graph.argtypes = [H, ctypes.c_int32]
     L.lbmd_autotune.argtypes = [H, ctypes.c_int32, ctypes.c_char_p, _I32, _D]
+    L.lbmd_batch_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(H)]
+    L.lbmd_batch_destroy.argtypes = [H]
+    L.lbmd_batch_attach.argtypes = [H, H, ctypes.c_int64, _I32]
+    L.lbmd_batch_detach.argtypes = [H, ctypes.c_int32]
+    L.lbmd_batch_step.argtypes = [H, ctypes.c_int64]
+    L.lbmd_batch_poll.argtypes = [H, ctypes.POINTER(ctypes.c_int64), _I32]
+    L.lbmd_batch_last_error.argtypes = [H]
+    L.lbmd_batch_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("lbmd_get_step", "lbmd_last_error"):
+        if name not in ("lbmd_get_step", "lbmd_last_error", "lbmd_batch_last_error"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -252,3 +261,58 @@ class Sim:
     @property
     def step_index(self):
         return load().lbmd_get_step(self._h)
+
+
+EMPTY, RUNNING, DONE, FAILED = 0, 1, 2, 3
+
+
+class Batch:
+    """A multi-lattice batch: attached Sim handles advance together
+    (lbmd_batch_* in include/lbmd.h)."""
+
+    def __init__(self, max_jobs=32, noise=False, stream=None):
+        L = load()
+        self._h = ctypes.c_void_p()
+        rc = L.lbmd_batch_create(max_jobs, int(bool(noise)), ctypes.c_void_p(stream or 0), ctypes.byref(self._h))
+        if rc != OK:
+            raise LbmdError(rc, "lbmd_batch_create failed")
+        self.max_jobs = max_jobs
+        self.jobs = {}
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LbmdError(rc, load().lbmd_batch_last_error(self._h).decode())
+        return rc
+
+    def attach(self, sim, nsteps):
+        slot = ctypes.c_int32()
+        self._check(load().lbmd_batch_attach(self._h, sim._h, nsteps, ctypes.byref(slot)))
+        self.jobs[slot.value] = sim
+        return slot.value
+
+    def detach(self, slot):
+        self._check(load().lbmd_batch_detach(self._h, slot))
+        return self.jobs.pop(slot)
+
+    def step(self, n=1):
+        self._check(load().lbmd_batch_step(self._h, n))
+
+    def poll(self):
+        """(steps[max_jobs], state[max_jobs]) with state EMPTY/RUNNING/DONE/FAILED."""
+        steps = np.empty(self.max_jobs, dtype=np.int64)
+        state = np.empty(self.max_jobs, dtype=np.int32)
+        self._check(load().lbmd_batch_poll(self._h, steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                           state.ctypes.data_as(_I32)))
+        return steps, state
+
+    def close(self):
+        if self._h:
+            load().lbmd_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self.jobs = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

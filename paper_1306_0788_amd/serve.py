@@ -1,0 +1,133 @@
+"""Serving independent simulations with continuous batching.
+
+A request loop admits jobs (lattice, G, particles, step count) as they
+arrive, in arrival order, whenever a batch slot is free and the job's device
+footprint fits the memory budget; admitted jobs keep their lattices and
+particles resident and advance together in the multi-lattice batch
+(lbmd_batch_*: one launch sequence per step for all jobs, captured in a HIP
+graph); a job leaves the batch, and frees its memory, when it reaches its
+step count or fails numerically, and queued jobs take its place.  The same
+jobs can be run one by one on the single-job path for comparison.
+
+Time-to-completion of a job = completion time - arrival time (queueing,
+set-up, stepping).  Aggregate MLUPS = lattice site updates of all completed
+steps / (last completion - first arrival).
+"""
+import time
+from collections import deque
+
+import numpy as np
+
+from . import lbmd
+
+# device bytes per site: two population buffers (2 x 38 x 4), the density
+# field (2 x 4), node records (16 x 4), node forces (4 x 4), touched-node mask
+BYTES_PER_SITE = 2 * 38 * 4 + 2 * 4 + 16 * 4 + 4 * 4 + 1 / 8
+BYTES_PER_PARTICLE = 4 * 3 * 8 + 4 + 8 * 4 + 64
+
+
+def footprint(job):
+    """Device bytes a job holds while resident."""
+    return int(np.prod(job["shape"]) * BYTES_PER_SITE + len(job["x"]) * BYTES_PER_PARTICLE)
+
+
+def make_sim(job, kernel=lbmd.KERNEL_AUTO, check_every=0):
+    sim = lbmd.Sim(job["shape"], precision=lbmd.FP32, forcing=lbmd.FORCE_PAPER, kernel=kernel,
+                   G=((0.0, job["G"]), (job["G"], 0.0)), gamma=job["gamma"], kappa=job["kappa"],
+                   mass=job["mass"], kT=job.get("kT", 0.0), seed=job.get("seed", 0), rho_init=job["rho"],
+                   check_every=check_every)
+    if len(job["x"]):
+        sim.set_particles(job["x"])
+    return sim
+
+
+def serve_batched(jobs, arrivals, max_jobs=32, mem_budget=64 << 30, chunk=10, log=None):
+    """Continuous batching.  Returns one record per job: arrival, admitted,
+    done (s from the start), steps completed, failed flag."""
+    n = len(jobs)
+    rec = [dict(arrival=float(arrivals[i]), admitted=None, done=None, steps=0, failed=False) for i in range(n)]
+    pending = deque(range(n))
+    queue = deque()
+    batch = lbmd.Batch(max_jobs=max_jobs, noise=False)
+    active = {}  # slot -> (job index, sim, bytes)
+    used = 0
+    finished = 0
+    t0 = time.perf_counter()
+    try:
+        while finished < n:
+            now = time.perf_counter() - t0
+            while pending and arrivals[pending[0]] <= now:
+                queue.append(pending.popleft())
+            while queue and len(active) < max_jobs and used + footprint(jobs[queue[0]]) <= mem_budget:
+                i = queue.popleft()
+                sim = make_sim(jobs[i], kernel=lbmd.KERNEL_FUSED)
+                slot = batch.attach(sim, jobs[i]["steps"])
+                b = footprint(jobs[i])
+                active[slot] = (i, sim, b)
+                used += b
+                rec[i]["admitted"] = time.perf_counter() - t0
+            if queue and not active:
+                raise RuntimeError("job %d does not fit the memory budget" % queue[0])
+            if not active:
+                time.sleep(max(0.0, min(0.01, arrivals[pending[0]] - now)) if pending else 0.0)
+                continue
+            batch.step(chunk)
+            steps, state = batch.poll()
+            t = time.perf_counter() - t0
+            for slot in list(active):
+                if state[slot] in (lbmd.DONE, lbmd.FAILED):
+                    i, sim, b = active.pop(slot)
+                    batch.detach(slot)
+                    rec[i]["done"] = t
+                    rec[i]["steps"] = int(steps[slot])
+                    rec[i]["failed"] = state[slot] == lbmd.FAILED
+                    sim.close()
+                    used -= b
+                    finished += 1
+                    if log:
+                        log("job %d (%s) %s at %.3f s" % (i, jobs[i]["shape"][0],
+                                                         "failed" if rec[i]["failed"] else "done", t))
+    finally:
+        batch.close()
+    return rec
+
+
+def serve_one_by_one(jobs, arrivals, check_every=10):
+    """The same stream served one job at a time on the single-job path
+    (default organisation and tiling, graph replay)."""
+    n = len(jobs)
+    rec = [dict(arrival=float(arrivals[i]), admitted=None, done=None, steps=0, failed=False) for i in range(n)]
+    t0 = time.perf_counter()
+    for i in range(n):
+        now = time.perf_counter() - t0
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        rec[i]["admitted"] = time.perf_counter() - t0
+        sim = make_sim(jobs[i], check_every=check_every)
+        sim.set_graph(True)
+        rc = sim.step_rc(jobs[i]["steps"])
+        st = sim.sync()
+        rec[i]["failed"] = rc != lbmd.OK or st != lbmd.OK
+        rec[i]["steps"] = int(jobs[i]["steps"]) if not rec[i]["failed"] else _failed_step(sim)
+        rec[i]["done"] = time.perf_counter() - t0
+        sim.close()
+    return rec
+
+
+def _failed_step(sim):
+    msg = sim.last_error()
+    try:
+        return int(msg.split("step ")[1].split()[0])
+    except (IndexError, ValueError):
+        return 0
+
+
+def summarize(jobs, rec):
+    done = [r for r in rec if not r["failed"]]
+    lat = np.array([r["done"] - r["arrival"] for r in done])
+    sites = sum(int(np.prod(jobs[i]["shape"])) * rec[i]["steps"] for i in range(len(jobs)))
+    span = max(r["done"] for r in rec) - min(r["arrival"] for r in rec)
+    return {"jobs": len(jobs), "completed": len(done), "failed": len(rec) - len(done),
+            "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+            "aggregate_MLUPS": sites / span / 1e6, "makespan_s": span}

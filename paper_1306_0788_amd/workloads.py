@@ -16,7 +16,15 @@ dataset):
   * chains: random walks of fixed bond length 0.97 started at uniform points,
     each new bead rejected while closer than `min_dist` to a bead already
     placed that is not its bonded predecessor; a chain that gets stuck is
-    removed and restarted elsewhere.
+    removed and restarted elsewhere;
+  * emulsion jobs (serving): cubic box L = round(exp(U[ln 32, ln 128])),
+    non-overlapping A droplets (periodic distance > r1 + r2 + 2) with radius
+    U[4, 12] until the droplet volume reaches a fraction U[0.1, 0.3];
+    rho_A = 0.1 + 1.8 s, rho_B = 0.1 + 1.8 (1 - s) with the smooth indicator
+    s = (1 - tanh((d - R)/2))/2 of the nearest droplet; G_AB = U[1.6, 2.2];
+    log-uniform 100..10,000 particles uniform in the box, kappa_A = -0.05
+    (drawn to the A droplets), gamma = 1, m = 100; 500 steps; arrivals a
+    Poisson stream of 20 jobs/s.
 """
 import math
 
@@ -195,3 +203,52 @@ def particles_for(w, shape=None):
         return free_particles(n, shape, w["seed"], spec["min_dist"]), None
     nch = max(1, int(round(spec["nchains"] * scale)))
     return chains(nch, spec["nbeads"], shape, w["seed"], spec["bond"], spec["min_dist"])
+
+
+def emulsion_job(seed, index):
+    """Parameters and inputs of serving job `index` of stream `seed`:
+    dict(shape, G, rho [2][N], x [n][3], kappa, gamma, mass, steps)."""
+    g = rng(seed * 1000003 + index)
+    L = int(round(math.exp(g.uniform(math.log(32.0), math.log(128.0)))))
+    target = g.uniform(0.1, 0.3) * L ** 3
+    cs = np.zeros((0, 3))
+    rs = np.zeros(0)
+    vol = 0.0
+    for _ in range(10000):
+        if vol >= target:
+            break
+        R = g.uniform(4.0, 12.0)
+        c = g.random(3) * L
+        d = cs - c
+        d -= L * np.round(d / L)
+        if np.all(np.sqrt((d * d).sum(axis=1)) >= rs + R + 2.0):
+            cs = np.vstack([cs, c])
+            rs = np.append(rs, R)
+            vol += 4.0 / 3.0 * math.pi * R ** 3
+    centres, radii = list(cs), list(rs)
+    s = np.zeros((L, L, L))
+    for c, R in zip(centres, radii):
+        # the indicator is below 1e-5 beyond R + 12: work on the wrapped box
+        h = int(math.ceil(R + 12.0))
+        idx, off = [], []
+        for a in range(3):
+            i0 = int(math.floor(c[a])) - h
+            raw = np.arange(i0, i0 + 2 * h + 2)
+            if len(raw) > L:
+                raw = np.arange(L)
+            idx.append(np.mod(raw, L))
+            d = raw - c[a]
+            off.append(d - L * np.round(d / L))
+        dz, dy, dx = np.meshgrid(off[2], off[1], off[0], indexing="ij")
+        ind = 0.5 * (1.0 - np.tanh((np.sqrt(dx * dx + dy * dy + dz * dz) - R) / 2.0))
+        sub = np.ix_(idx[2], idx[1], idx[0])
+        s[sub] = np.maximum(s[sub], ind)
+    rho = np.stack([0.1 + 1.8 * s, 0.1 + 1.8 * (1.0 - s)]).reshape(2, -1)
+    n = int(round(math.exp(g.uniform(math.log(100.0), math.log(10000.0)))))
+    return dict(shape=(L, L, L), G=float(g.uniform(1.6, 2.2)), rho=rho, x=g.random((n, 3)) * L,
+                kappa=(-0.05, 0.0), gamma=1.0, mass=100.0, steps=500, droplets=len(radii))
+
+
+def poisson_arrivals(n, rate, seed):
+    """Arrival times (s) of n jobs of a Poisson stream of the given rate."""
+    return np.cumsum(rng(seed + 7).exponential(1.0 / rate, n))
