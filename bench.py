@@ -205,6 +205,40 @@ def accuracy_study(workload, steps):
                       "against the FP64 oracle)", "results": res}), flush=True)
 
 
+def _emulsion(args):
+    from paper_1306_0788_amd import workloads
+    return workloads.emulsion_job(*args)
+
+
+def serving(njobs, rate, seed, max_jobs, mem_gib, one_by_one, jobs):
+    """The serving workload: a Poisson stream of emulsion jobs served with
+    continuous batching (and, if asked, one job at a time)."""
+    from paper_1306_0788_amd import serve, workloads
+    arrivals = workloads.poisson_arrivals(njobs, rate, seed)
+    print("serve: %d jobs at %.0f/s, continuous batching (%d slots, %d GiB)" % (njobs, rate, max_jobs, mem_gib),
+          file=sys.stderr, flush=True)
+    count = [0]
+
+    def progress(msg):
+        count[0] += 1
+        if count[0] % 64 == 0:
+            print("serve: %d jobs finished (%s)" % (count[0], msg), file=sys.stderr, flush=True)
+
+    rb = serve.serve_batched(jobs, arrivals, max_jobs=max_jobs, mem_budget=mem_gib << 30, chunk=10, log=progress)
+    out = {"jobs": njobs, "arrival_rate_per_s": rate, "steps_per_job": jobs[0]["steps"],
+           "lattice_sites_mean": float(np.mean([np.prod(j["shape"]) for j in jobs])),
+           "slots": max_jobs, "memory_budget_GiB": mem_gib, "batched": serve.summarize(jobs, rb)}
+    if one_by_one:
+        print("serve: the same stream one job at a time", file=sys.stderr, flush=True)
+        count[0] = 0
+        rs = serve.serve_one_by_one(jobs, arrivals, log=progress)
+        out["one_by_one"] = serve.summarize(jobs, rs)
+        fb = [r["failed"] for r in rb]
+        fs = [r["failed"] for r in rs]
+        out["same_failures"] = fb == fs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +254,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="advance the timed steps by replaying captured HIP graphs")
     ap.add_argument("--autotune", action="store_true", help="pick the tiling with the library's autotuner first")
+    ap.add_argument("--serve-jobs", type=int, default=512, help="jobs in the served Poisson stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-mem-gib", type=int, default=64)
+    ap.add_argument("--serve-one-by-one", action="store_true",
+                    help="also serve the stream one job at a time for comparison")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving workload")
     ap.add_argument("--accuracy", type=int, default=None, metavar="STEPS",
                     help="instead of timing: error of every storage form against the FP64 step after STEPS steps")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -236,6 +277,14 @@ def main():
               "which is not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    jobs = None
+    if args.serve_jobs > 0:
+        # inputs of the served stream, generated before the GPU is touched
+        import multiprocessing as mp
+        print("bench: generating %d serving jobs" % args.serve_jobs, file=sys.stderr, flush=True)
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+            jobs = pool.map(_emulsion, [(5, i) for i in range(args.serve_jobs)], chunksize=4)
+
     from paper_1306_0788_amd import workloads
     onset = workloads.WORKLOADS[args.workload].get("onset")
     if args.steps is None:
@@ -248,6 +297,11 @@ def main():
     import torch
     from paper_1306_0788_amd import lbmd
     assert torch.cuda.is_available(), "no GPU visible"
+    if args.serve_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"served": serving(args.serve_jobs, args.serve_rate, 5, args.serve_slots,
+                                            args.serve_mem_gib, args.serve_one_by_one, jobs)}), flush=True)
+        return
     torch.cuda.set_device(0)
     # a dedicated stream (the current one may be the null stream, handle 0,
     # which the library would replace by a stream of its own)
@@ -332,6 +386,10 @@ def main():
                      "kernel_ms_avg": round(kavg_s * 1e3, 5), "bytes_per_site": 76 * s_bytes},
     }
     sim.close()
+    del sim
+    if jobs is not None:
+        line["served"] = serving(args.serve_jobs, args.serve_rate, 5, args.serve_slots, args.serve_mem_gib,
+                                 args.serve_one_by_one, jobs)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.workload)

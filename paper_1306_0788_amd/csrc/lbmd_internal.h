@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -94,6 +95,35 @@ __device__ __forceinline__ uint16_t dev_encode_sr(float v, uint32_t r, dev16<tru
   // normal range of binary16 (below it, about 6e-5, it rounds to nearest)
   const uint32_t t = (b + (r & 0x1fffu)) & ~0x1fffu;
   return dev_encode(__builtin_bit_cast(float, t), (dev16<true>*)nullptr);
+}
+
+// ------------------------------------------------------------ particle positions
+// Position wrapped into [0, L).  Far outside the box (only after a numerical
+// failure: velocities diverge before they turn non-finite) x - L floor(x/L)
+// is inexact, so such values are folded with the exact fmod; NaN stays NaN
+// (the failure check sees it).
+__host__ __device__ inline double wrapd(double x, double L) {
+  x -= L * std::floor(x / L);
+  if (x >= L) x -= L;
+  if (x < 0.0) x += L;
+  if (!(x >= 0.0 && x < L) && std::isfinite(x)) {
+    x = std::fmod(x, L);
+    if (x < 0.0) x += L;
+    if (!(x < L)) x = 0.0;
+  }
+  return x;
+}
+
+// Lattice cell of a coordinate floor(x) for a box of n sites: 0 <= f < n
+// for every position the integrator produces; anything else (non-finite or
+// out of range after a numerical failure, which is flagged on its own) is
+// mapped into the box so that no node index leaves the lattice.
+__host__ __device__ inline int cell_coord(double f, int n) {
+  if (f >= 0.0 && f < double(n)) return int(f);
+  if (!std::isfinite(f)) return 0;
+  double g = std::fmod(f, double(n));
+  if (g < 0.0) g += double(n);
+  return (g >= 0.0 && g < double(n)) ? int(g) : 0;
 }
 
 // ------------------------------------------------------------ Philox4x32-10

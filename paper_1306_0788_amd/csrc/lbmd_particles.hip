@@ -23,13 +23,6 @@
 namespace lbmd {
 
 
-__device__ __forceinline__ double wrapd(double x, double L) {
-  x -= L * floor(x / L);
-  if (x >= L) x -= L;
-  if (x < 0.0) x += L;
-  return x;
-}
-
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * floor(d / L + 0.5); }
 
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
@@ -37,7 +30,7 @@ __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >
 __device__ __forceinline__ void interp(const double* x, int nx, int ny, int nz, int64_t (&node)[8], double (&W)[8]) {
   const double fx = floor(x[0]), fy = floor(x[1]), fz = floor(x[2]);
   const double dx = x[0] - fx, dy = x[1] - fy, dz = x[2] - fz;
-  const int ix = int(fx), iy = int(fy), iz = int(fz);
+  const int ix = cell_coord(fx, nx), iy = cell_coord(fy, ny), iz = cell_coord(fz, nz);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
@@ -51,8 +44,9 @@ __device__ __forceinline__ int cell_index(const double* x, const PartArgs& A) {
   const double L[3] = {double(A.nx), double(A.ny), double(A.nz)};
   int c[3];
   for (int a = 0; a < 3; ++a) {
-    int q = int(x[a] / L[a] * A.ncell[a]);
-    c[a] = q < 0 ? 0 : (q >= A.ncell[a] ? A.ncell[a] - 1 : q);
+    // clamped before the conversion (non-finite positions go to cell 0)
+    const double q = x[a] / L[a] * A.ncell[a];
+    c[a] = q >= 0.0 && q < double(A.ncell[a]) ? int(q) : (q >= double(A.ncell[a]) ? A.ncell[a] - 1 : 0);
   }
   return (c[2] * A.ncell[1] + c[1]) * A.ncell[0] + c[0];
 }

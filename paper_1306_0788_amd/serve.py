@@ -92,7 +92,7 @@ def serve_batched(jobs, arrivals, max_jobs=32, mem_budget=64 << 30, chunk=10, lo
     return rec
 
 
-def serve_one_by_one(jobs, arrivals, check_every=10):
+def serve_one_by_one(jobs, arrivals, check_every=10, log=None):
     """The same stream served one job at a time on the single-job path
     (default organisation and tiling, graph replay)."""
     n = len(jobs)
@@ -111,6 +111,9 @@ def serve_one_by_one(jobs, arrivals, check_every=10):
         rec[i]["steps"] = int(jobs[i]["steps"]) if not rec[i]["failed"] else _failed_step(sim)
         rec[i]["done"] = time.perf_counter() - t0
         sim.close()
+        if log:
+            log("job %d (%s) %s at %.3f s" % (i, jobs[i]["shape"][0], "failed" if rec[i]["failed"] else "done",
+                                             rec[i]["done"]))
     return rec
 
 

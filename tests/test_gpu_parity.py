@@ -178,3 +178,20 @@ def test_invalid_parameters_rejected():
         s.set_pair_potential(lbmd.PAIR_DH, (1.0, 5.0, 1.0))  # cut-off above half the box
     with pytest.raises(lbmd.LbmdError):
         s.set_particles([[1.0, np.nan, 2.0]])
+
+
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_stepping_on_after_a_failure_stays_in_bounds(kernel):
+    """Regression: after a numerical failure the particle velocities diverge
+    before they turn non-finite, and positions far outside the box once gave
+    node indices outside the lattice.  A job far above the spinodal (G = 4)
+    with particles and WCA pairs is stepped well past its failure without
+    polling; the failure stays latched at its first step."""
+    c = Case((24, 20, 16), FP32, PAPER, kernel, G=4.0, gamma=1.0, npart=200, vel_amp=0.05,
+             kappa=((0.5, -0.5),), mass=(1.0,), wca=(1.0, 1.0), min_dist=1.2)
+    print("stepping past a failure, kernel %d" % kernel, flush=True)
+    g = c.gpu_sim()
+    g.step(120)
+    assert g.sync() == lbmd.EUNSTABLE
+    first = int(g.last_error().split("step ")[1].split()[0])
+    assert first < 100
