@@ -46,17 +46,32 @@ int bfail(lbmd_batch_s* b, int code, const char* msg) {
   } while (0)
 
 // Rebuild the job table from the occupied slots (in slot order) and upload
-// it.  The stream is idle here, so the pinned copies can be rewritten.
+// it.  The stream is idle here, so the pinned copies can be rewritten.  The z
+// chunk is common to the table: 16 planes (long z marches; the three-plane
+// start of a march is paid once per chunk) unless the tiles would then not
+// fill the fused kernel's grid, in which case it is halved (down to 2) --
+// a lone small lattice gets the parallelism, a full table the long marches.
+// The fused pass gives the same results for any chunk.
 int upload(lbmd_batch_s* b) {
   BHIP(b, hipStreamSynchronize(b->stream));
   b->row_slot.clear();
+  int tz = 16;
+  for (; tz > 2; tz /= 2) {
+    int64_t t = 0;
+    for (int s = 0; s < b->max_jobs; ++s)
+      if (const lbmd_ctx* h = b->job[s]) {
+        const int z = std::min(tz, h->p.nz);
+        t += int64_t((h->p.nx + 63) / 64) * ((h->p.ny + BATCH_TY - 1) / BATCH_TY) * ((h->p.nz + z - 1) / z);
+      }
+    if (t >= BATCH_FLUID_GRID) break;
+  }
   int64_t tiles = 0, pblk = 0, fix = 0;
   for (int s = 0; s < b->max_jobs; ++s) {
     lbmd_ctx* h = b->job[s];
     if (!h) continue;
     BatchJob& J = b->tab_host[b->row_slot.size()];
     std::memset(&J, 0, sizeof J);
-    batch_fill_fluid(h, J);
+    batch_fill_fluid(h, J, tz);
     if (h->np > 0) batch_fill_particles(h, J);
     J.target = b->target[s];
     J.tile_begin = tiles;

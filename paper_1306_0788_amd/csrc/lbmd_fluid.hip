@@ -1088,7 +1088,7 @@ __global__ void k_finalize_batch(const BatchJob* __restrict__ jobs, const BatchH
   finalize_sums(J.red_fluid, J.nblk, J.red_part, J.npblk, J.red_out, J.nflag, J.step);
 }
 
-constexpr int BATCH_FLUID_GRID = 2048, BATCH_FIX_GRID = 1024;
+constexpr int BATCH_FIX_GRID = 1024;
 
 hipError_t batch_fluid_pass(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, bool noise) {
   if (noise)
@@ -1122,9 +1122,9 @@ hipError_t batch_gather(hipStream_t st, const BatchJob* jobs, const BatchHeader*
   return hipGetLastError();
 }
 
-// The job's constants, buffers and fused tiling (4 rows per tile, the z
-// chunk of the default rule).
-void batch_fill_fluid(const lbmd_ctx* h, BatchJob& J) {
+// The job's constants, buffers and fused tiling: 4 rows per tile and z
+// chunks of at most tz planes (the batch picks tz for the whole table).
+void batch_fill_fluid(const lbmd_ctx* h, BatchJob& J, int tz) {
   J.K = consts<float>(h);
   J.step = h->step_dev;
   J.f[0] = (const float*)h->f[0];
@@ -1140,8 +1140,7 @@ void batch_fill_fluid(const lbmd_ctx* h, BatchJob& J) {
   J.flag_list = h->flag_list;
   J.tiles_x = (h->p.nx + 63) / 64;
   const int64_t tiles_y = (h->p.ny + BATCH_TY - 1) / BATCH_TY;
-  const int tz = pow2_floor(std::max<int64_t>(1, J.tiles_x * tiles_y * h->p.nz / 256));
-  J.tz = std::min(16, std::max(2, std::min(tz, h->p.nz)));
+  J.tz = std::max(1, std::min(tz, h->p.nz));
   J.nblk = int(J.tiles_x * tiles_y * ((h->p.nz + J.tz - 1) / J.tz));
   J.nfixblk = h->np > 0 ? (h->flag_cap + 255) / 256 : 0;
 }

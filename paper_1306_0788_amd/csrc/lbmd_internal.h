@@ -279,6 +279,7 @@ struct BatchHeader {
   int64_t ntiles, npblk, nfixblk;
 };
 constexpr int BATCH_TY = 4;
+constexpr int BATCH_FLUID_GRID = 2048;  // blocks of the fused batch kernel
 // launchers (lbmd_fluid.hip / lbmd_particles.hip); grids are fixed so that a
 // captured step serves any composition of the job table
 hipError_t batch_fluid_pass(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, bool noise);
@@ -288,7 +289,7 @@ hipError_t batch_particles_begin(hipStream_t st, const BatchJob* jobs, const Bat
 hipError_t batch_particles_couple(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr);
 hipError_t batch_particles_end(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr);
 hipError_t batch_gather(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr, int max_jobs, int64_t* out);
-void batch_fill_fluid(const lbmd_ctx* h, BatchJob& J);      // K, buffers, tiling
+void batch_fill_fluid(const lbmd_ctx* h, BatchJob& J, int tz);  // K, buffers, tiling
 void batch_fill_particles(const lbmd_ctx* h, BatchJob& J);  // A, particle buffers
 }  // namespace lbmd
 

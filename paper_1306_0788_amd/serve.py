@@ -58,35 +58,41 @@ def serve_batched(jobs, arrivals, max_jobs=32, mem_budget=64 << 30, chunk=10, lo
             now = time.perf_counter() - t0
             while pending and arrivals[pending[0]] <= now:
                 queue.append(pending.popleft())
-            while queue and len(active) < max_jobs and used + footprint(jobs[queue[0]]) <= mem_budget:
+            # the device first: a chunk of steps for the resident jobs ...
+            if active:
+                batch.step(chunk)
+            # ... while the host sets up the jobs it can admit (their set-up
+            # runs on their own streams) ...
+            new = []
+            while queue and len(active) + len(new) < max_jobs and used + footprint(jobs[queue[0]]) <= mem_budget:
                 i = queue.popleft()
-                sim = make_sim(jobs[i], kernel=lbmd.KERNEL_FUSED)
-                slot = batch.attach(sim, jobs[i]["steps"])
-                b = footprint(jobs[i])
-                active[slot] = (i, sim, b)
-                used += b
-                rec[i]["admitted"] = time.perf_counter() - t0
-            if queue and not active:
+                new.append((i, make_sim(jobs[i], kernel=lbmd.KERNEL_FUSED)))
+                used += footprint(jobs[i])
+            if queue and not active and not new:
                 raise RuntimeError("job %d does not fit the memory budget" % queue[0])
-            if not active:
-                time.sleep(max(0.0, min(0.01, arrivals[pending[0]] - now)) if pending else 0.0)
-                continue
-            batch.step(chunk)
-            steps, state = batch.poll()
-            t = time.perf_counter() - t0
-            for slot in list(active):
-                if state[slot] in (lbmd.DONE, lbmd.FAILED):
-                    i, sim, b = active.pop(slot)
-                    batch.detach(slot)
-                    rec[i]["done"] = t
-                    rec[i]["steps"] = int(steps[slot])
-                    rec[i]["failed"] = state[slot] == lbmd.FAILED
-                    sim.close()
-                    used -= b
-                    finished += 1
-                    if log:
-                        log("job %d (%s) %s at %.3f s" % (i, jobs[i]["shape"][0],
-                                                         "failed" if rec[i]["failed"] else "done", t))
+            # ... then waits for the chunk and retires finished jobs
+            if active:
+                steps, state = batch.poll()
+                t = time.perf_counter() - t0
+                for slot in list(active):
+                    if state[slot] in (lbmd.DONE, lbmd.FAILED):
+                        i, sim, b = active.pop(slot)
+                        batch.detach(slot)
+                        rec[i]["done"] = t
+                        rec[i]["steps"] = int(steps[slot])
+                        rec[i]["failed"] = state[slot] == lbmd.FAILED
+                        sim.close()
+                        used -= b
+                        finished += 1
+                        if log:
+                            log("job %d (%s) %s at %.3f s" % (i, jobs[i]["shape"][0],
+                                                             "failed" if rec[i]["failed"] else "done", t))
+            for i, sim in new:
+                slot = batch.attach(sim, jobs[i]["steps"])
+                active[slot] = (i, sim, footprint(jobs[i]))
+                rec[i]["admitted"] = time.perf_counter() - t0
+            if not active and pending:
+                time.sleep(max(0.0, min(0.01, arrivals[pending[0]] - (time.perf_counter() - t0))))
     finally:
         batch.close()
     return rec
