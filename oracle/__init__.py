@@ -55,15 +55,17 @@ class Params(ctypes.Structure):
         ("wca_sigma", ctypes.c_double), ("wca_eps", ctypes.c_double),
         ("fene_k", ctypes.c_double), ("fene_R0", ctypes.c_double),
         ("dh_kappa", ctypes.c_double), ("dh_rc", ctypes.c_double), ("dh_lB", ctypes.c_double),
+        ("lambda_fs", (ctypes.c_double * 2) * MAXTYPES),
     ]
 
 
 def make_params(shape, tau=(1.0, 1.0), G=((0.0, 1.6), (1.6, 0.0)), forcing=FORCE_PAPER,
                 gamma=0.0, kT=0.0, seed=0, kappa=((0.0, 0.0),), mass=(1.0,), charge=(0.0,),
-                wca=None, fene=None, dh=None, mrt=None):
+                wca=None, fene=None, dh=None, mrt=None, lambda_fs=None):
     """Build the C parameter struct.  shape = (nx, ny, nz).
     wca = (sigma, eps); fene = (k, R0); dh = (kappa_D, r_c, l_B);
-    mrt = (lambda_bulk, lambda_shear, lambda_mom, lambda_ghost) or None (BGK)."""
+    mrt = (lambda_bulk, lambda_shear, lambda_mom, lambda_ghost) or None (BGK);
+    lambda_fs = per-type (lambda_A, lambda_B) of the fluid solvation force."""
     p = Params()
     p.nx, p.ny, p.nz = (int(s) for s in shape)
     p.forcing = forcing
@@ -86,6 +88,9 @@ def make_params(shape, tau=(1.0, 1.0), G=((0.0, 1.6), (1.6, 0.0)), forcing=FORCE
         p.fene_on, (p.fene_k, p.fene_R0) = 1, fene
     if dh is not None:
         p.dh_on, (p.dh_kappa, p.dh_rc, p.dh_lB) = 1, dh
+    if lambda_fs is not None:
+        for t in range(len(lambda_fs)):
+            p.lambda_fs[t][0], p.lambda_fs[t][1] = lambda_fs[t]
     return p
 
 
@@ -130,6 +135,7 @@ def lib():
         L.orc_site_collide.restype = ctypes.c_int
         L.orc_node_fields.argtypes = [_PP, _D, ctypes.c_int64, _D, _D]
         L.orc_coupling_force_one.argtypes = [_PP, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, ctypes.c_int64, _D]
+        L.orc_solvation_fluid_force.argtypes = [_PP, _D, ctypes.c_int64, _D, _I32, _D, _D]
         L.orc_particle_force_at.argtypes = [_PP, ctypes.c_int64, _D, ctypes.c_int64, _D, _D, _I32,
                                             ctypes.c_int64, _D]
         _lib = L
@@ -331,3 +337,19 @@ class Sim:
 
     def fluid_momentum(self):
         return moments(self.P, self.f)[1].sum(axis=1)
+
+
+def solvation_fluid_force(P, rho, x, types=None):
+    """Fluid solvation force of particles at x on the nodes, fs [2][3][N],
+    and the momentum returned to each particle, back [n][3]."""
+    N = P.nx * P.ny * P.nz
+    rho = _c64(np.asarray(rho, dtype=np.float64).reshape(2, N))
+    x = _c64(np.asarray(x, dtype=np.float64).reshape(-1, 3))
+    n = len(x)
+    t = None if types is None else np.ascontiguousarray(types, dtype=np.int32)
+    fs = np.zeros((2, 3, N))
+    back = np.zeros((max(n, 1), 3))
+    lib().orc_solvation_fluid_force(ctypes.byref(P), rho.ctypes.data_as(_D), n, x.ctypes.data_as(_D),
+                                     None if t is None else t.ctypes.data_as(_I32), fs.ctypes.data_as(_D),
+                                     back.ctypes.data_as(_D))
+    return fs, back[:n]

@@ -10,8 +10,11 @@
  *   S4  particle half kick and drift                  (velocity Verlet, dt=1)
  *   S5  friction + solvation + random force            (Sec. 2, Eqs. NEWTON
  *       at the new positions, trilinear interpolation    and solvation_kappa)
- *   S6  opposite force spread onto the 8 nodes         (Sec. 2, momentum
- *                                                       returned by the same
+ *   S5b fluid solvation force on the nodes of each     (Sec. 2, Eq.
+ *       particle's cell, its momentum returned to the     solvation_lambda)
+ *       particle
+ *   S6  opposite coupling force spread onto the 8      (Sec. 2, momentum
+ *       nodes                                            returned by the same
  *                                                       interpolation)
  *   S7  collision in mode space with forcing and noise (Appendix, Eqs. collis,
  *                                                       feq, MODES, forcing
@@ -272,6 +275,46 @@ void orc_interp_weights(const double* x, int32_t nx, int32_t ny, int32_t nz, int
   }
 }
 
+void orc_solvation_fluid_force(const orc_params* P, const double* rho, int64_t np, const double* x,
+                               const int32_t* type, double* fs, double* back) {
+  int64_t N = nsites(P);
+  int L[3] = {P->nx, P->ny, P->nz};
+  for (int64_t p = 0; p < np; p++) {
+    int t = type ? type[p] : 0;
+    double lam[2] = {P->lambda_fs[t][0], P->lambda_fs[t][1]};
+    double b[3] = {0.0, 0.0, 0.0};
+    double fl[3];
+    for (int a = 0; a < 3; a++) fl[a] = floor(x[3 * p + a]);
+    for (int k = 0; k < 8; k++) {
+      int o[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
+      double d[3];
+      int n[3];
+      for (int a = 0; a < 3; a++) {
+        d[a] = x[3 * p + a] - (fl[a] + o[a]); /* from the vertex to the particle */
+        n[a] = pmod((int)fl[a] + o[a], L[a]);
+      }
+      int64_t site = ((int64_t)n[2] * P->ny + n[1]) * P->nx + n[0];
+      /* links pointing into the half space of the particle, each weighted
+         by (r' - r)/|r' - r|^2 */
+      double S[3] = {0.0, 0.0, 0.0};
+      for (int i = 1; i < ORC_Q; i++) {
+        double dot = d[0] * C[i][0] + d[1] * C[i][1] + d[2] * C[i][2];
+        if (dot > 0.0) {
+          double c2 = C[i][0] * C[i][0] + C[i][1] * C[i][1] + C[i][2] * C[i][2];
+          for (int a = 0; a < 3; a++) S[a] += C[i][a] / c2;
+        }
+      }
+      for (int c = 0; c < 2; c++)
+        for (int a = 0; a < 3; a++) {
+          double force = -lam[c] * rho[c * N + site] * S[a];
+          fs[((int64_t)c * 3 + a) * N + site] += force;
+          b[a] -= force;
+        }
+    }
+    for (int a = 0; a < 3; a++) back[3 * p + a] = b[a];
+  }
+}
+
 /* Pair potentials: 0 = WCA (Sec. 2.. examples, with the usual +eps shift),
    1 = screened Debye-Hueckel, 2 = FENE bond.  qq = product of charges. */
 double orc_pair_energy(const orc_params* P, int32_t kind, double r, double qq) {
@@ -381,7 +424,7 @@ static int check_params(const orc_params* P) {
    gsc  [2][3]  Shan-Chen force per component, gP [3] particle force (total)
    out  [2][19] post-collision populations */
 static void collide_site(const orc_params* P, int64_t step, int64_t site, const double* fin,
-                         const double* gsc, const double* gP, double* out) {
+                         const double* gsc, const double* gP, const double* gfs, double* out) {
   static int basis_ready = 0;
   static double E[ORC_Q][ORC_Q], B[ORC_Q];
   if (!basis_ready) {
@@ -399,10 +442,11 @@ static void collide_site(const orc_params* P, int64_t step, int64_t site, const 
   }
   double rt = rho[0] + rho[1];
   /* particle back-reaction split between the components by mass fraction
-     (the paper does not say which component receives it) */
+     (the paper does not say which component receives it); the fluid
+     solvation force (if any) acts on its own component */
   double g[2][3];
   for (int c = 0; c < 2; c++)
-    for (int a = 0; a < 3; a++) g[c][a] = gsc[3 * c + a] + rho[c] / rt * gP[a];
+    for (int a = 0; a < 3; a++) g[c][a] = gsc[3 * c + a] + rho[c] / rt * gP[a] + (gfs ? gfs[3 * c + a] : 0.0);
 
   /* equilibrium velocity per component */
   double ueq[2][3];
@@ -562,7 +606,7 @@ int orc_site_collide(const orc_params* P, int64_t step, const double* f, int64_t
   }
   for (int c = 0; c < 2; c++)
     for (int a = 0; a < 3; a++) gsc[3 * c + a] = -rho[c] * (P->G[c][0] * Ns[0][a] + P->G[c][1] * Ns[1][a]);
-  collide_site(P, step, site, fin, gsc, gP, out);
+  collide_site(P, step, site, fin, gsc, gP, NULL, out);
   return ORC_OK;
 }
 
@@ -578,6 +622,8 @@ int orc_step(const orc_params* P, int64_t step, double* f, int64_t np, double* x
   double* gsc = malloc(sizeof(double) * 6 * N);
   double* uc = malloc(sizeof(double) * 3 * N);
   double* gP = calloc(3 * N, sizeof(double));
+  double* gfs = calloc(6 * N, sizeof(double));
+  double* back = calloc(3 * (np > 0 ? np : 1), sizeof(double));
   double* fnew = malloc(sizeof(double) * 2 * ORC_Q * N);
 
   /* S1 */
@@ -639,11 +685,8 @@ int orc_step(const orc_params* P, int64_t step, double* f, int64_t np, double* x
       Fc[3 * p + a] = -P->gamma * (v[3 * p + a] - up[a]) -
                       (P->kappa[t][0] * gr[0][a] + P->kappa[t][1] * gr[1][a]) + R[a];
   }
-  if (np > 0) {
-    if (orc_conservative_forces(P, np, x, type, nbonds, bonds, F) != ORC_OK) status = ORC_EUNSTABLE;
-    for (int64_t p = 0; p < 3 * np; p++) F[p] += Fc[p];
-  }
-  /* S6 */
+  /* S6: the interpolated coupling force goes back through the same
+     weights */
   for (int64_t p = 0; p < np; p++) {
     int64_t node[8];
     double W[8];
@@ -651,14 +694,23 @@ int orc_step(const orc_params* P, int64_t step, double* f, int64_t np, double* x
     for (int k = 0; k < 8; k++)
       for (int a = 0; a < 3; a++) gP[a * N + node[k]] -= W[k] * Fc[3 * p + a];
   }
+  /* S5b: fluid solvation force at step n's densities; the particle gets
+     back what it gave, so Fc becomes the total force from the fluid */
+  orc_solvation_fluid_force(P, rho, np, x, type, gfs, back);
+  for (int64_t p = 0; p < 3 * np; p++) Fc[p] += back[p];
+  if (np > 0) {
+    if (orc_conservative_forces(P, np, x, type, nbonds, bonds, F) != ORC_OK) status = ORC_EUNSTABLE;
+    for (int64_t p = 0; p < 3 * np; p++) F[p] += Fc[p];
+  }
   /* S7 + S8 */
   for (int64_t s = 0; s < N; s++) {
-    double fin[2 * ORC_Q], out[2 * ORC_Q], gs[6], gp[3];
+    double fin[2 * ORC_Q], out[2 * ORC_Q], gs[6], gp[3], gf[6];
     for (int c = 0; c < 2; c++)
       for (int i = 0; i < ORC_Q; i++) fin[c * ORC_Q + i] = f[((int64_t)c * ORC_Q + i) * N + s];
     for (int q = 0; q < 6; q++) gs[q] = gsc[(int64_t)q * N + s];
     for (int a = 0; a < 3; a++) gp[a] = gP[a * N + s];
-    collide_site(P, step, s, fin, gs, gp, out);
+    for (int q = 0; q < 6; q++) gf[q] = gfs[(int64_t)q * N + s];
+    collide_site(P, step, s, fin, gs, gp, gf, out);
     int xx, yy, zz;
     coords_of(P, s, &xx, &yy, &zz);
     for (int c = 0; c < 2; c++)
@@ -675,6 +727,6 @@ int orc_step(const orc_params* P, int64_t step, double* f, int64_t np, double* x
       if (!isfinite(x[3 * p + a]) || !isfinite(v[3 * p + a])) status = ORC_EUNSTABLE;
     }
   }
-  free(rho); free(j); free(Ns); free(gsc); free(uc); free(gP); free(fnew);
+  free(rho); free(j); free(Ns); free(gsc); free(uc); free(gP); free(gfs); free(back); free(fnew);
   return status;
 }

@@ -45,6 +45,8 @@ typedef struct {
   double wca_sigma, wca_eps;
   double fene_k, fene_R0;
   double dh_kappa, dh_rc, dh_lB;
+  double lambda_fs[ORC_MAXTYPES][2]; /* fluid solvation lambda_A, lambda_B per
+                                        type (Sec. 2, Eq. solvation_lambda)  */
 } orc_params;
 
 /* ---- tables and single-site pieces (exposed for the pins) ---- */
@@ -112,6 +114,15 @@ void orc_coupling_force_one(const orc_params* P, int64_t step, const double* f, 
 void orc_particle_force_at(const orc_params* P, int64_t step, const double* f, int64_t np,
                            const double* x, const double* v, const int32_t* type, int64_t site,
                            double* gP /*[3]*/);
+/* Fluid solvation force (Sec. 2, Eq. solvation_lambda).  Each particle acts
+ * on the 8 vertices r of its lattice cell: at r, with d = x_p - r, it adds
+ * -lambda_zeta(type) rho_zeta(r) sum_j c_j / |c_j|^2 over the D3Q19 links j
+ * whose direction makes an angle in [0, 90) degrees with d (Theta read as
+ * 0 < cos <= 1, i.e. d . c_j > 0).  The momentum it gives the fluid is
+ * returned to the particle (back [np][3] = minus its total over the 8 nodes
+ * and both components).  rho: [2][N]; fs: [2][3][N] is accumulated into.   */
+void orc_solvation_fluid_force(const orc_params* P, const double* rho, int64_t np, const double* x,
+                               const int32_t* type, double* fs, double* back);
 /* u_c and grad rho_zeta at one node (the quantities the particles see).    */
 void orc_node_fields(const orc_params* P, const double* f, int64_t site,
                      double* uc /*[3]*/, double* grad /*[2][3]*/);
