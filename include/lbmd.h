@@ -156,6 +156,16 @@ int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double
 int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, const double* mass,
                             const double* charge);
 
+/* Fluid solvation force (Sec. 2, Eq. solvation_lambda): lambda [ntypes][2]
+   = (lambda_A, lambda_B) per particle type (types >= ntypes get 0; ntypes =
+   0 switches the force off).  Each particle acts on the 8 vertices r of its
+   lattice cell with -lambda_zeta rho_zeta(r) sum_j c_j/|c_j|^2 over the
+   D3Q19 links j with (x_p - r) . c_j > 0, and receives the opposite of the
+   total, so momentum is conserved; lbmd_get_particles' fcoup then includes
+   that return.  Allocates 8 values per site on first use.  Errors:
+   LBMD_EINVAL, LBMD_ENOMEM, LBMD_EDEVICE, LBMD_ESTATE (in a batch). */
+int lbmd_set_solvation_lambda(lbmd_handle h, int32_t ntypes, const double* lambda);
+
 /* Switch a conservative particle interaction on (params != NULL) or off
    (params == NULL).  The WCA form is the one the paper uses for excluded
    volume, with the usual +eps shift; the screened Debye-Hueckel form is the

@@ -455,6 +455,7 @@ int lbmd_destroy(lbmd_handle h) {
   if (h->rho) (void)hipFree(h->rho);
   if (h->rec) (void)hipFree(h->rec);
   if (h->gP) (void)hipFree(h->gP);
+  if (h->gS) (void)hipFree(h->gS);
   dfree(h->mask);
   free_particles(h);
   free_bonds(h);
@@ -556,6 +557,32 @@ int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, 
     h->types.kappa[t][1] = kappa[2 * t + 1];
     h->types.mass[t] = mass[t];
     h->types.charge[t] = charge ? charge[t] : 0.0;
+  }
+  return LBMD_OK;
+}
+
+int lbmd_set_solvation_lambda(lbmd_handle h, int32_t ntypes, const double* lambda) {
+  if (h && h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
+  if (!h || ntypes < 0 || ntypes > LBMD_MAX_TYPES || (ntypes > 0 && !lambda))
+    return fail(h, LBMD_EINVAL, "set_solvation_lambda: bad arguments");
+  for (int t = 0; t < 2 * ntypes; ++t)
+    if (!std::isfinite(lambda[t])) return fail(h, LBMD_EINVAL, "set_solvation_lambda: non-finite lambda");
+  graph_invalidate(h);
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  int on = 0;
+  for (int t = 0; t < LBMD_MAX_TYPES; ++t)
+    for (int c = 0; c < 2; ++c) {
+      h->types.lambda[t][c] = t < ntypes ? lambda[2 * t + c] : 0.0;
+      on |= h->types.lambda[t][c] != 0.0;
+    }
+  h->types.lambda_on = on;
+  if (on && !h->gS) {
+    HIPCHECK(h, hipMalloc(&h->gS, 8 * h->N * h->c_bytes));
+    HIPCHECK(h, hipMemsetAsync(h->gS, 0, 8 * h->N * h->c_bytes, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+  } else if (!on && h->gS) {
+    (void)hipFree(h->gS);
+    h->gS = nullptr;
   }
   return LBMD_OK;
 }

@@ -335,10 +335,13 @@ __global__ void k_export(const S* __restrict__ src, const arith_t<S>* __restrict
 
 // ------------------------------------------------------------ layouts
 // Per-node records (one 64-byte line per node in FP32, two in FP64), written
-// at the nodes the particles touch: N_A (3), N_B (3), u_c (3).  The
-// particle force density accumulated at a node: gP[4 * s + a].
+// at the nodes the particles touch: N_A (3), N_B (3), u_c (3), rho_A,
+// rho_B.  The particle force density accumulated at a node: gP[4 * s + a];
+// the fluid solvation sums U_zeta (if any lambda is set): gS[8 * s + 3 zeta
+// + a].
 constexpr int REC = 16;
 constexpr int GPS = 4;
+constexpr int GSS = 8;
 
 __global__ void k_zero_words(uint32_t* __restrict__ w, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -534,6 +537,8 @@ __device__ __forceinline__ void fused_tile(const S* __restrict__ src_, S* __rest
           r[3 + a] = NB[a];
           r[6 + a] = uc[a];
         }
+        r[9] = m.rho[0];
+        r[10] = m.rho[1];
       }
       SiteOut<C> o;
       o.rho[0] = m.rho[0];
@@ -576,7 +581,7 @@ template <class S, int FORCING, bool NOISE>
 __device__ __forceinline__ void fix_node(const S* __restrict__ src, S* __restrict__ dst, FluidConsts<arith_t<S>> K,
                                          const int32_t* __restrict__ list, const int32_t* __restrict__ nlist,
                                          const arith_t<S>* __restrict__ rec, arith_t<S>* __restrict__ gP,
-                                         uint32_t* __restrict__ mask, int64_t t) {
+                                         arith_t<S>* __restrict__ gS, uint32_t* __restrict__ mask, int64_t t) {
   using C = arith_t<S>;
   load_step(K);
   if (t >= *nlist) return;
@@ -593,7 +598,13 @@ __device__ __forceinline__ void fix_node(const S* __restrict__ src, S* __restric
     gP[s * GPS + a] = C(0);
   }
   mask[s >> 5] = 0u;
-  collide<C, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s));
+  C gu[6];
+  if (gS)
+    for (int q = 0; q < 6; ++q) {
+      gu[q] = gS[s * GSS + q];
+      gS[s * GSS + q] = C(0);
+    }
+  collide<C, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s), gS ? gu : nullptr);
   store<S, C>(make_pops<S>(dst, N, K.rho0, K.srkey), uint32_t(s), f);
 }
 
@@ -601,8 +612,9 @@ template <class S, int FORCING, bool NOISE>
 __global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __restrict__ dst, FluidConsts<arith_t<S>> K,
                                              const int32_t* __restrict__ list, const int32_t* __restrict__ nlist,
                                              const arith_t<S>* __restrict__ rec, arith_t<S>* __restrict__ gP,
-                                             uint32_t* __restrict__ mask) {
-  fix_node<S, FORCING, NOISE>(src, dst, K, list, nlist, rec, gP, mask, int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+                                             arith_t<S>* __restrict__ gS, uint32_t* __restrict__ mask) {
+  fix_node<S, FORCING, NOISE>(src, dst, K, list, nlist, rec, gP, gS, mask,
+                              int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------ split path
@@ -693,6 +705,8 @@ __global__ __launch_bounds__(64 * TY) void k_moments(const S* __restrict__ src_,
           r[3 + a] = NB[a];
           r[6 + a] = (o.j[a] + C(0.5) * gsc) * inv;
         }
+        r[9] = o.rho[0];
+        r[10] = o.rho[1];
       }
       if (!moments_ok(o)) flag_unstable(status, bad, 1u, K.step);
       acc[0] += o.rho[0];
@@ -715,7 +729,7 @@ template <class S, int TY, int FORCING, bool NOISE>
 __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_, S* __restrict__ dst_,
                                                       const arith_t<S>* __restrict__ rho, FluidConsts<arith_t<S>> K,
                                                       int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
-                                                      arith_t<S>* __restrict__ gP) {
+                                                      arith_t<S>* __restrict__ gP, arith_t<S>* __restrict__ gS) {
   using C = arith_t<S>;
   load_step(K);
   __shared__ C ring[4][2][TY + 2][66];
@@ -758,14 +772,22 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
       const int64_t s = z * plane + int64_t(y) * nx + x;
       pull<S, C>(src, x, y, z, nx, ny, nz, f);
       nsum_ring<C, TY>(ring, k & 3, (k + 1) & 3, (k + 2) & 3, wv, lane, NA, NB);
-      C gp[3] = {0, 0, 0};
+      C gp[3] = {0, 0, 0}, gu[6];
+      bool fs = false;
       if (mask && ((mask[s >> 5] >> (s & 31)) & 1u)) {
         for (int a = 0; a < 3; ++a) {
           gp[a] = gP[s * GPS + a];
           gP[s * GPS + a] = C(0);
         }
+        if (gS) {
+          fs = true;
+          for (int q = 0; q < 6; ++q) {
+            gu[q] = gS[s * GSS + q];
+            gS[s * GSS + q] = C(0);
+          }
+        }
       }
-      const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K);
+      const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K, fs ? gu : nullptr);
       relax_site<C, FORCING, NOISE>(f, m, K, uint32_t(s));
       store<S, C>(dst, uint32_t(s), f, K.nt);
     }
@@ -976,13 +998,14 @@ static hipError_t pass_b_t(lbmd_ctx* h) {
   if (organisation(h) == LBMD_KERNEL_FUSED) {
     if (h->np > 0)
       hipLaunchKernelGGL((k_fix<S, FORCING, NOISE>), dim3((h->flag_cap + 255) / 256), dim3(256), 0, h->stream, src,
-                         dst, K, h->flag_list, h->nflag, (const C*)h->rec, (C*)h->gP, h->mask);
+                         dst, K, h->flag_list, h->nflag, (const C*)h->rec, (C*)h->gP, (C*)h->gS, h->mask);
   } else {
     const Launch L = tiles(h);
     const uint32_t* mask = h->np > 0 ? h->mask : nullptr;
     if (hipError_t e = prof_begin(h)) return e;
     LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_collide<S, TYV, FORCING, NOISE>), dim3(L.nblk), dim3(64 * TYV), 0,
-                                        h->stream, src, dst, (const C*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (C*)h->gP));
+                                        h->stream, src, dst, (const C*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (C*)h->gP,
+                                        (C*)h->gS));
     if (hipError_t e = prof_end(h)) return e;
     if (h->np > 0) {
       const int64_t words = (h->N + 31) / 32;
@@ -1072,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_fix_batch(const BatchJob* __restrict__ 
     if (!batch_active(J)) continue;
     const int par = int(*J.step & 1);
     fix_node<float, LBMD_FORCE_PAPER, NOISE>(J.f[par], const_cast<float*>(J.f[1 - par]), J.K, J.flag_list, J.nflag,
-                                             J.rec, J.gP, J.mask, (u - J.fix_begin) * 256 + threadIdx.x);
+                                             J.rec, J.gP, J.gS, J.mask, (u - J.fix_begin) * 256 + threadIdx.x);
   }
 }
 
@@ -1132,6 +1155,7 @@ void batch_fill_fluid(const lbmd_ctx* h, BatchJob& J, int tz) {
   J.mask = h->np > 0 ? h->mask : nullptr;
   J.rec = (float*)h->rec;
   J.gP = (float*)h->gP;
+  J.gS = (float*)h->gS;
   J.red_fluid = h->red_fluid;
   J.red_out = h->red_out;
   J.status = h->status;

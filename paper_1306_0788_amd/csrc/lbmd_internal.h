@@ -185,7 +185,9 @@ struct ParticleTypes {
   double kappa[LBMD_MAX_TYPES][2];
   double mass[LBMD_MAX_TYPES];
   double charge[LBMD_MAX_TYPES];
+  double lambda[LBMD_MAX_TYPES][2];  // fluid solvation lambda_A, lambda_B
   int32_t ntypes;
+  int32_t lambda_on;  // any lambda != 0
 };
 
 struct PairParams {
@@ -256,6 +258,7 @@ struct BatchJob {
   uint32_t* mask;  // nullptr without particles
   float* rec;
   float* gP;
+  float* gS;  // fluid solvation sums (nullptr without lambda)
   double* red_fluid;
   double* red_part;
   double* red_out;
@@ -322,8 +325,9 @@ struct lbmd_ctx {
   int32_t* flag_list = nullptr;
   int32_t* nflag = nullptr;  // device counter
   int64_t flag_cap = 0;
-  void* rec = nullptr;  // [N][16]: N_A(3), N_B(3), u_c(3) at touched nodes
+  void* rec = nullptr;  // [N][16]: N_A(3), N_B(3), u_c(3), rho_A, rho_B at touched nodes
   void* gP = nullptr;   // [N][4]: particle force density accumulated at nodes
+  void* gS = nullptr;   // [N][8]: fluid solvation sums U_A(3), U_B(3) (with lambda only)
 
   // particles (always float64)
   int64_t np = 0, np_cap = 0;

@@ -274,11 +274,49 @@ __global__ __launch_bounds__(256) void k_pairs(PartArgs A, const double* __restr
 // gradients (N / c_s^2) from the node records, friction + solvation (Eq.
 // solvation_kappa) + random force; total force F = coupling + conservative;
 // the opposite coupling force spread onto the 8 nodes.
+// Fluid solvation force of particle p (Sec. 2, Eq. solvation_lambda) on the
+// 8 vertices of its cell: at vertex r, with d = x_p - r, the links j with
+// d . c_j > 0 (Theta read as 0 < cos <= 1) contribute c_j / |c_j|^2 to S_r;
+// U_zeta(r) += lambda_zeta S_r (the collision applies -rho_zeta U_zeta) and
+// the particle gets back sum_r sum_zeta lambda_zeta rho_zeta(r) S_r, the
+// momentum its force gave the fluid.  The link test is exact in FP64 (the
+// c_j are 0 or +-1).
+template <class C>
+__device__ __forceinline__ void solvation_lambda(const PartArgs& A, const double (&xp)[3], int t,
+                                                 const int64_t (&node)[8], const C* __restrict__ rec,
+                                                 C* __restrict__ gS, double (&back)[3]) {
+  const double la = A.T.lambda[t][0], lb = A.T.lambda[t][1];
+  const double fl[3] = {floor(xp[0]), floor(xp[1]), floor(xp[2])};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double d[3] = {xp[0] - (fl[0] + (k & 1)), xp[1] - (fl[1] + ((k >> 1) & 1)),
+                         xp[2] - (fl[2] + ((k >> 2) & 1))};
+    double S[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
+      const double dot = d[0] * cx + d[1] * cy + d[2] * cz;
+      const double wgt = (cx * cx + cy * cy + cz * cz) == 1 ? 1.0 : 0.5;
+      if (dot > 0.0) {
+        S[0] += wgt * cx;
+        S[1] += wgt * cy;
+        S[2] += wgt * cz;
+      }
+    }
+    const double ra = double(rec[node[k] * 16 + 9]), rb = double(rec[node[k] * 16 + 10]);
+    for (int a = 0; a < 3; ++a) {
+      atomicAdd(&gS[node[k] * 8 + a], C(la * S[a]));
+      atomicAdd(&gS[node[k] * 8 + 3 + a], C(lb * S[a]));
+      back[a] += (la * ra + lb * rb) * S[a];
+    }
+  }
+}
+
 template <class C>
 __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict__ x, const double* __restrict__ v,
                                            double* __restrict__ F, double* __restrict__ Fc,
                                            const double* __restrict__ Fcons, const int32_t* __restrict__ type,
-                                           const C* __restrict__ rec, C* __restrict__ gP,
+                                           const C* __restrict__ rec, C* __restrict__ gP, C* __restrict__ gS,
                                            const int32_t* __restrict__ perm, uint32_t* status, long long* bad,
                                            int64_t tid) {
   if (tid >= A.np) return;
@@ -305,17 +343,19 @@ __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict_
     const double amp = sqrt(2.0 * A.kT * A.gamma);
     for (int a = 0; a < 3; ++a) R[a] *= amp;
   }
-  double fc[3];
+  double fc[3], back[3] = {0, 0, 0};
+  if (gS && (A.T.lambda[t][0] != 0.0 || A.T.lambda[t][1] != 0.0)) solvation_lambda<C>(A, xp, t, node, rec, gS, back);
   bool ok = true;
   for (int a = 0; a < 3; ++a) {
     fc[a] = -A.gamma * (v[3 * p + a] - up[a]) - (A.T.kappa[t][0] * gA[a] + A.T.kappa[t][1] * gB[a]) + R[a];
-    Fc[3 * p + a] = fc[a];
-    const double Ft = fc[a] + (Fcons ? Fcons[3 * p + a] : 0.0);
+    // Fc: everything the fluid exerts on the particle
+    Fc[3 * p + a] = fc[a] + back[a];
+    const double Ft = fc[a] + back[a] + (Fcons ? Fcons[3 * p + a] : 0.0);
     F[3 * p + a] = Ft;
     ok = ok && isfinite(Ft);
   }
   if (!ok) flag_unstable(status, bad, 2u, A.step);
-  // momentum returned to the fluid by the same interpolation
+  // the interpolated part goes back to the fluid by the same interpolation
 #pragma unroll
   for (int k = 0; k < 8; ++k)
     for (int a = 0; a < 3; ++a) atomicAdd(&gP[node[k] * 4 + a], C(-W[k] * fc[a]));
@@ -326,9 +366,10 @@ __global__ __launch_bounds__(256) void k_couple(PartArgs A, const double* __rest
                                                 const double* __restrict__ v, double* __restrict__ F,
                                                 double* __restrict__ Fc, const double* __restrict__ Fcons,
                                                 const int32_t* __restrict__ type, const C* __restrict__ rec,
-                                                C* __restrict__ gP, const int32_t* __restrict__ perm,
+                                                C* __restrict__ gP, C* __restrict__ gS, const int32_t* __restrict__ perm,
                                                 uint32_t* status, long long* bad) {
-  couple_one<C>(A, x, v, F, Fc, Fcons, type, rec, gP, perm, status, bad, int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+  couple_one<C>(A, x, v, F, Fc, Fcons, type, rec, gP, gS, perm, status, bad,
+                int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
 }
 
 __device__ __forceinline__ void end_one(PartArgs A, const double* __restrict__ x, double* __restrict__ v,
@@ -426,10 +467,12 @@ hipError_t particles_forces(lbmd_ctx* h) {
   const double* Fcons = cons ? h->Fcons : nullptr;
   if (h->p.precision == LBMD_FP64)
     hipLaunchKernelGGL(k_couple<double>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, Fcons,
-                       h->type, (const double*)h->rec, (double*)h->gP, h->cell_perm, h->status, h->bad_step);
+                       h->type, (const double*)h->rec, (double*)h->gP, (double*)h->gS, h->cell_perm, h->status,
+                       h->bad_step);
   else
     hipLaunchKernelGGL(k_couple<float>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, Fcons,
-                       h->type, (const float*)h->rec, (float*)h->gP, h->cell_perm, h->status, h->bad_step);
+                       h->type, (const float*)h->rec, (float*)h->gP, (float*)h->gS, h->cell_perm, h->status,
+                       h->bad_step);
   return hipGetLastError();
 }
 
@@ -481,7 +524,7 @@ __global__ __launch_bounds__(256) void k_couple_batch(const BatchJob* __restrict
   for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
     const BatchJob& J = jobs[batch_job_of<&BatchJob::pblk_begin>(jobs, nj, u)];
     if (!batch_active(J)) continue;
-    couple_one<float>(J.A, J.x, J.v, J.F, J.Fc, nullptr, J.type, J.rec, J.gP, nullptr, J.status, J.bad,
+    couple_one<float>(J.A, J.x, J.v, J.F, J.Fc, nullptr, J.type, J.rec, J.gP, J.gS, nullptr, J.status, J.bad,
                       (u - J.pblk_begin) * 256 + threadIdx.x);
   }
 }

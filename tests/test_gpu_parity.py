@@ -195,3 +195,31 @@ def test_stepping_on_after_a_failure_stays_in_bounds(kernel):
     assert g.sync() == lbmd.EUNSTABLE
     first = int(g.last_error().split("step ")[1].split()[0])
     assert first < 100
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-11), (FP32, 1e-5)])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_fluid_solvation_force(precision, tol, kernel):
+    """The fluid solvation force (lambda per type and component) with its
+    momentum return, next to friction and kappa solvation, two particle
+    types: 5 steps against the oracle."""
+    c = Case((28, 22, 18), precision, PAPER, kernel, G=1.3, gamma=0.6, npart=60, vel_amp=0.03,
+             kappa=((0.2, -0.1), (-0.15, 0.25)), mass=(20.0, 30.0), lambda_fs=((0.08, -0.05), (-0.03, 0.06)))
+    g, o = run_pair(c, 5)
+    compare(c, g, o, tol * 5, tol * 5, "lambda")
+
+
+def test_invariant_with_fluid_solvation_on_gpu():
+    c = Case((24, 20, 16), FP64, PAPER, FUSED, G=1.4, gamma=0.8, npart=50, vel_amp=0.05,
+             kappa=((0.3, -0.1),), mass=(400.0,), lambda_fs=((0.05, -0.04),))
+    g = c.gpu_sim()
+    first = None
+    for k in range(40):
+        g.step(1)
+        red, st = g.reductions()
+        if first is None:
+            first = red.copy()
+        inv, inv0 = red[2:5] + red[5:8], first[2:5] + first[5:8]
+        assert np.abs(inv - inv0).max() < 1e-12, (k, inv - inv0)
+    x, v, F, Fc = g.particles()
+    assert np.abs(Fc).max() > 0
