@@ -156,6 +156,19 @@ int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double
 int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, const double* mass,
                             const double* charge);
 
+/* Multiple-relaxation-time collision (Appendix, Eqs. collis and MODES; the
+   forcing source term in its general form with lambda_M, lambda_s,
+   lambda_b): enable != 0 relaxes the momentum modes of each component with
+   lambda_mom, the bulk mode with lambda_bulk, the five shear modes with
+   lambda_shear and the nine kinetic modes with lambda_ghost (each in
+   (-2, 0); BGK is every eigenvalue -1/tau), in place of the BGK relaxation
+   with tau[].  Fluctuations (kT > 0) take each mode's own eigenvalue.  Needs
+   LBMD_FORCE_PAPER; the step then uses the two-pass organisation (a kernel
+   explicitly set to LBMD_KERNEL_FUSED is refused).  enable = 0 returns to
+   BGK.  Errors: LBMD_EINVAL, LBMD_ESTATE (in a batch). */
+int lbmd_set_mrt(lbmd_handle h, int32_t enable, double lambda_bulk, double lambda_shear, double lambda_mom,
+                 double lambda_ghost);
+
 /* Fluid solvation force (Sec. 2, Eq. solvation_lambda): lambda [ntypes][2]
    = (lambda_A, lambda_B) per particle type (types >= ntypes get 0; ntypes =
    0 switches the force off).  Each particle acts on the 8 vertices r of its

@@ -561,6 +561,27 @@ int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, 
   return LBMD_OK;
 }
 
+int lbmd_set_mrt(lbmd_handle h, int32_t enable, double lambda_bulk, double lambda_shear, double lambda_mom,
+                 double lambda_ghost) {
+  if (h && h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
+  if (!h) return LBMD_EINVAL;
+  if (enable) {
+    const double l[4] = {lambda_mom, lambda_bulk, lambda_shear, lambda_ghost};
+    for (double v : l)
+      if (!(v > -2.0 && v < 0.0)) return fail(h, LBMD_EINVAL, "set_mrt: every eigenvalue must lie in (-2, 0)");
+    if (h->p.forcing != LBMD_FORCE_PAPER) return fail(h, LBMD_EINVAL, "set_mrt: needs the paper's forcing");
+    if (h->p.kernel == LBMD_KERNEL_FUSED) return fail(h, LBMD_EINVAL, "set_mrt: MRT runs in the two-pass organisation");
+  }
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  graph_invalidate(h);
+  h->mrt = enable != 0;
+  h->mrt_lam[0] = lambda_mom;
+  h->mrt_lam[1] = lambda_bulk;
+  h->mrt_lam[2] = lambda_shear;
+  h->mrt_lam[3] = lambda_ghost;
+  return LBMD_OK;
+}
+
 int lbmd_set_solvation_lambda(lbmd_handle h, int32_t ntypes, const double* lambda) {
   if (h && h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (!h || ntypes < 0 || ntypes > LBMD_MAX_TYPES || (ntypes > 0 && !lambda))

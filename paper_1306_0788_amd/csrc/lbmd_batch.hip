@@ -193,6 +193,7 @@ int lbmd_batch_attach(lbmd_batch b, lbmd_handle h, int64_t nsteps, int32_t* slot
   if (h->latched) return bfail(b, LBMD_ESTATE, "attach: the handle has a latched failure");
   if (h->p.precision != LBMD_FP32 || h->p.forcing != LBMD_FORCE_PAPER || (h->p.kT > 0.0) != b->noise)
     return bfail(b, LBMD_EINVAL, "attach: a batch runs FP32 populations, the paper's forcing and one noise setting");
+  if (h->mrt) return bfail(b, LBMD_EINVAL, "attach: batch jobs use the BGK collision");
   if (h->pair.wca_on || h->pair.dh_on || h->pair.fene_on || h->nbonds > 0)
     return bfail(b, LBMD_EINVAL, "attach: batch jobs have no pair potentials or bonds");
   if (h->device != b->device) return bfail(b, LBMD_EINVAL, "attach: the handle lives on another device");

@@ -725,7 +725,7 @@ __global__ __launch_bounds__(64 * TY) void k_moments(const S* __restrict__ src_,
 // Pass C: collision and streaming of every site, the particle force applied
 // where a particle touches; the density ring is filled from the density
 // field written by pass P (two values per site instead of 38).
-template <class S, int TY, int FORCING, bool NOISE>
+template <class S, int TY, int FORCING, bool NOISE, bool MRT>
 __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_, S* __restrict__ dst_,
                                                       const arith_t<S>* __restrict__ rho, FluidConsts<arith_t<S>> K,
                                                       int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
@@ -788,7 +788,7 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
         }
       }
       const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K, fs ? gu : nullptr);
-      relax_site<C, FORCING, NOISE>(f, m, K, uint32_t(s));
+      relax_site<C, FORCING, NOISE, MRT>(f, m, K, uint32_t(s));
       store<S, C>(dst, uint32_t(s), f, K.nt);
     }
     if (z + 2 <= z1) load_border(z + 2, (k + 3) & 3);
@@ -841,6 +841,7 @@ FluidConsts<arith_t<S>> consts(const lbmd_ctx* h) {
   }
   K.kT = C(h->p.kT);
   K.rho0 = Storage<S>::deviation ? C(h->p.rho0) : C(0);
+  for (int q = 0; q < 4; ++q) K.lam[q] = C(h->mrt_lam[q]);
   K.srkey = 0;  // set from the device step counter in the kernel
   K.forcing = h->p.forcing;
   K.noise = h->p.kT > 0.0;
@@ -895,6 +896,7 @@ hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out) { LBMD_BY_STORA
 
 // organisation actually used this step
 static int organisation(const lbmd_ctx* h) {
+  if (h->mrt) return LBMD_KERNEL_TWOPASS;  // the MRT collision is built into the two-pass kernels only
   if (h->p.kernel != LBMD_KERNEL_AUTO) return h->p.kernel;
   // the fused pass re-collides every touched node with scattered accesses
   // (about 76 per node); the split passes cost one extra read of the
@@ -1003,9 +1005,15 @@ static hipError_t pass_b_t(lbmd_ctx* h) {
     const Launch L = tiles(h);
     const uint32_t* mask = h->np > 0 ? h->mask : nullptr;
     if (hipError_t e = prof_begin(h)) return e;
-    LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_collide<S, TYV, FORCING, NOISE>), dim3(L.nblk), dim3(64 * TYV), 0,
-                                        h->stream, src, dst, (const C*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (C*)h->gP,
-                                        (C*)h->gS));
+    if (FORCING == LBMD_FORCE_PAPER && h->mrt) {
+      LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_collide<S, TYV, LBMD_FORCE_PAPER, NOISE, true>), dim3(L.nblk),
+                                          dim3(64 * TYV), 0, h->stream, src, dst, (const C*)h->rho, K, L.tz, L.tiles_x,
+                                          h->xcd, mask, (C*)h->gP, (C*)h->gS));
+    } else {
+      LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_collide<S, TYV, FORCING, NOISE, false>), dim3(L.nblk), dim3(64 * TYV), 0,
+                                          h->stream, src, dst, (const C*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask,
+                                          (C*)h->gP, (C*)h->gS));
+    }
     if (hipError_t e = prof_end(h)) return e;
     if (h->np > 0) {
       const int64_t words = (h->N + 31) / 32;

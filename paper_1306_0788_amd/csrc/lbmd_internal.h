@@ -230,6 +230,7 @@ struct FluidConsts {
   int nt;  // non-temporal hint on the population stores
   C rho0;  // reference density of deviation storage (0 otherwise)
   uint32_t srkey;  // per-step key of the stochastic rounding of deviations (load_step)
+  C lam[4];        // MRT eigenvalues {momentum, bulk, shear, kinetic} (MRT kernels only)
 };
 
 // Step index of the launch from the device counter (so that a captured step
@@ -365,6 +366,8 @@ struct lbmd_ctx {
   std::string err;
 
   lbmd_batch_s* batch = nullptr;  // attached to a multi-lattice batch
+  bool mrt = false;                // MRT collision (two-pass organisation)
+  double mrt_lam[4] = {0, 0, 0, 0};  // momentum, bulk, shear, kinetic
 
   // replay of captured two-step sequences, one per ping-pong parity
   bool use_graph = false;

@@ -111,6 +111,66 @@ __device__ __forceinline__ void relax(C (&f)[19], C rho, const C (&u)[3], const 
   }
 }
 
+// Eigenvalue of mode k under MRT: lam = {momentum, bulk, shear, kinetic}.
+template <class C>
+__device__ __forceinline__ C mode_lambda(int k, const C (&lam)[4]) {
+  return k <= 3 ? lam[0] : (k == 4 ? lam[1] : (k <= 9 ? lam[2] : lam[3]));
+}
+
+// MRT relaxation of one component (Appendix, Eqs. collis and MODES): mode k
+// relaxes with its eigenvalue lambda_k towards the mode of f^eq(rho, u), and
+// the forcing source term of the Appendix is added in its general form,
+//   Delta_i = 3 w_i (2 + lambda_M)/2 g.c_i
+//             + 9/2 w_i [G : c_i c_i - c_s^2 tr G],
+//   G = (2 + lambda_s)/2 (u g + g u - 2/3 u.g 1) + (2 + lambda_b)/3 u.g 1.
+// Since the mode basis is complete and w-orthogonal, the relaxation is
+// applied as f_i += w_i sum_k e_ki lambda_k (m_k - m^eq_k) / b_k.
+template <class C>
+__device__ __forceinline__ void relax_mrt(C (&f)[19], C rho, const C (&u)[3], const C (&g)[3], const C (&lam)[4]) {
+  const C usq = C(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  C d[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const C cu = C(D3Q19::cx[i]) * u[0] + C(D3Q19::cy[i]) * u[1] + C(D3Q19::cz[i]) * u[2];
+    d[i] = f[i] - weight<C>(i) * rho * (C(1) + C(3) * cu + C(4.5) * cu * cu - usq);
+  }
+  C a[19];
+  a[0] = C(0);
+#pragma unroll
+  for (int k = 1; k < 19; ++k) {
+    C m = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+      if (mode_e(k, i) != 0) m += C(mode_e(k, i)) * d[i];
+    a[k] = mode_lambda<C>(k, lam) * m * (C(36) / C(mode_b36(k)));
+  }
+  const C ug = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+  const C fs = (C(2) + lam[2]) * C(0.5), fb = (C(2) + lam[1]) / C(3), fm = (C(2) + lam[0]) * C(0.5);
+  C G[3][3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x)
+#pragma unroll
+    for (int y = 0; y < 3; ++y)
+      G[x][y] = fs * (u[x] * g[y] + g[x] * u[y] - (x == y ? C(2) / C(3) * ug : C(0))) + (x == y ? fb * ug : C(0));
+  const C trG = G[0][0] + G[1][1] + G[2][2];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int c[3] = {D3Q19::cx[i], D3Q19::cy[i], D3Q19::cz[i]};
+    C s = 0;
+#pragma unroll
+    for (int k = 1; k < 19; ++k)
+      if (mode_e(k, i) != 0) s += C(mode_e(k, i)) * a[k];
+    C gc = 0, Gcc = 0;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      gc += C(c[x]) * g[x];
+#pragma unroll
+      for (int y = 0; y < 3; ++y) Gcc += C(c[x] * c[y]) * G[x][y];
+    }
+    f[i] += weight<C>(i) * (s + C(3) * fm * gc + C(4.5) * (Gcc - trG / C(3)));
+  }
+}
+
 // Macroscopic part of the collision: densities, raw momentum, forces and
 // the equilibrium velocity of each component.
 template <class C>
@@ -181,11 +241,16 @@ __device__ __forceinline__ void coupling_velocity(const Macro<C>& m, C (&uc)[3])
 }
 
 // Relaxation of both components (and fluctuations when NOISE).
-template <class C, int FORCING, bool NOISE>
+template <class C, int FORCING, bool NOISE, bool MRT = false>
 __device__ __forceinline__ void relax_site(C (&f)[2][19], const Macro<C>& m, const FluidConsts<C>& K,
                                            uint32_t site) {
-  relax<C, FORCING == LBMD_FORCE_PAPER>(f[0], m.rho[0], m.u[0], m.g[0], K.omega[0]);
-  relax<C, FORCING == LBMD_FORCE_PAPER>(f[1], m.rho[1], m.u[1], m.g[1], K.omega[1]);
+  if (MRT) {
+    relax_mrt<C>(f[0], m.rho[0], m.u[0], m.g[0], K.lam);
+    relax_mrt<C>(f[1], m.rho[1], m.u[1], m.g[1], K.lam);
+  } else {
+    relax<C, FORCING == LBMD_FORCE_PAPER>(f[0], m.rho[0], m.u[0], m.g[0], K.omega[0]);
+    relax<C, FORCING == LBMD_FORCE_PAPER>(f[1], m.rho[1], m.u[1], m.g[1], K.omega[1]);
+  }
   if (NOISE) {
     // fluctuations (Appendix, Eq. MODES): 3 shared momentum normals with
     // opposite sign for A and B, 15 per component for the bulk, shear and
@@ -194,17 +259,21 @@ __device__ __forceinline__ void relax_site(C (&f)[2][19], const Macro<C>& m, con
     C z[36];
 #pragma unroll
     for (int b = 0; b < 9; ++b) normals4<C>(K.seed, K.step, site, b, 0, &z[4 * b]);
+    // per-mode factor 1 - (1 + lambda_k)^2 (BGK: lambda_k = -1/tau)
     const C om = K.omega[0];
-    const C t = C(3) * K.kT * (C(1) - (C(1) - om) * (C(1) - om));
-    const C sc[2] = {csqrt(fmax(m.rho[0], C(0)) * t), csqrt(fmax(m.rho[1], C(0)) * t)};
-    const C sm = csqrt(fmax(m.rho[0] * m.rho[1] * m.inv_rt, C(0)) * t);
+    const C rA = fmax(m.rho[0], C(0)), rB = fmax(m.rho[1], C(0)), rM = fmax(m.rho[0] * m.rho[1] * m.inv_rt, C(0));
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       C a[19];
 #pragma unroll
-      for (int k = 1; k < 4; ++k) a[k] = (c == 0 ? sm : -sm) * z[k - 1] * C(6) / csqrt(C(mode_b36(k)));
-#pragma unroll
-      for (int k = 4; k < 19; ++k) a[k] = sc[c] * z[3 + 15 * c + (k - 4)] * C(6) / csqrt(C(mode_b36(k)));
+      for (int k = 1; k < 19; ++k) {
+        const C l1 = C(1) + (MRT ? mode_lambda<C>(k, K.lam) : -om);
+        const C t = C(3) * K.kT * (C(1) - l1 * l1);
+        if (k < 4)
+          a[k] = (c == 0 ? C(1) : C(-1)) * csqrt(rM * t) * z[k - 1] * C(6) / csqrt(C(mode_b36(k)));
+        else
+          a[k] = csqrt((c == 0 ? rA : rB) * t) * z[3 + 15 * c + (k - 4)] * C(6) / csqrt(C(mode_b36(k)));
+      }
 #pragma unroll
       for (int i = 0; i < 19; ++i) {
         C s = 0;

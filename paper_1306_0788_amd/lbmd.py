@@ -25,7 +25,8 @@ EXPORTS = ["lbmd_create", "lbmd_destroy", "lbmd_set_particles", "lbmd_set_partic
            "lbmd_get_particles", "lbmd_set_populations", "lbmd_reductions", "lbmd_get_step",
            "lbmd_last_error", "lbmd_set_tiling", "lbmd_kernel_timing", "lbmd_organisation", "lbmd_set_graph",
            "lbmd_autotune", "lbmd_batch_create", "lbmd_batch_destroy", "lbmd_batch_attach", "lbmd_batch_detach",
-           "lbmd_batch_step", "lbmd_batch_poll", "lbmd_batch_last_error", "lbmd_set_solvation_lambda"]
+           "lbmd_batch_step", "lbmd_batch_poll", "lbmd_batch_last_error", "lbmd_set_solvation_lambda",
+           "lbmd_set_mrt"]
 
 
 class LbmdError(RuntimeError):
@@ -66,6 +67,7 @@ def load():
     L.lbmd_set_particle_types.argtypes = [H, ctypes.c_int32, _D, _D, _D]
     L.lbmd_set_pair_potential.argtypes = [H, ctypes.c_int32, _D]
     L.lbmd_set_solvation_lambda.argtypes = [H, ctypes.c_int32, _D]
+    L.lbmd_set_mrt.argtypes = [H, ctypes.c_int32] + [ctypes.c_double] * 4
     L.lbmd_set_bonds.argtypes = [H, ctypes.c_int64, _I32]
     L.lbmd_step.argtypes = [H, ctypes.c_int64]
     L.lbmd_sync.argtypes = [H]
@@ -166,6 +168,13 @@ class Sim:
         mass = _f64(mass)
         charge = None if charge is None else _f64(charge)
         self._check(load().lbmd_set_particle_types(self._h, kappa.shape[0], _dp(kappa), _dp(mass), _dp(charge)))
+
+    def set_mrt(self, lambdas=None):
+        """lambdas = (bulk, shear, momentum, kinetic) eigenvalues, or None for BGK."""
+        if lambdas is None:
+            self._check(load().lbmd_set_mrt(self._h, 0, 0.0, 0.0, 0.0, 0.0))
+        else:
+            self._check(load().lbmd_set_mrt(self._h, 1, *[float(v) for v in lambdas]))
 
     def set_solvation_lambda(self, lambdas):
         """lambdas: per-type (lambda_A, lambda_B) of the fluid solvation force."""

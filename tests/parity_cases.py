@@ -21,7 +21,7 @@ class Case:
     def __init__(self, shape, precision=lbmd.FP64, forcing=lbmd.FORCE_PAPER, kernel=lbmd.KERNEL_FUSED,
                  G=1.6, tau=1.0, gamma=0.5, kappa=((0.0, 0.0),), mass=(1.0,), charge=(0.0,), kT=0.0, seed=1,
                  npart=64, min_dist=0.0, wca=None, fene=None, dh=None, chains=None, amp=0.01, vel_amp=0.0,
-                 positions=None, tiling=None, lambda_fs=None):
+                 positions=None, tiling=None, lambda_fs=None, mrt=None):
         self.shape = tuple(shape)
         self.N = int(np.prod(shape))
         self.precision, self.forcing, self.kernel = precision, forcing, kernel
@@ -31,6 +31,7 @@ class Case:
         self.wca, self.fene, self.dh = wca, fene, dh
         self.tiling = tiling
         self.lambda_fs = lambda_fs
+        self.mrt = mrt
         self.rho = workloads.initial_densities(self.shape, seed, amp).reshape(2, -1)
         self.bonds = None
         if positions is not None:
@@ -50,7 +51,7 @@ class Case:
                                   forcing=oracle.FORCE_SHIFT if self.forcing == lbmd.FORCE_SHIFT else oracle.FORCE_PAPER,
                                   gamma=self.gamma, kT=self.kT, seed=self.seed, kappa=self.kappa, mass=self.mass,
                                   charge=self.charge, wca=self.wca, fene=self.fene, dh=self.dh,
-                                  lambda_fs=self.lambda_fs)
+                                  lambda_fs=self.lambda_fs, mrt=self.mrt)
 
     def oracle_sim(self):
         return oracle.Sim(self.oracle_params(), self.rho, self.x, self.v, self.type, self.bonds)
@@ -75,6 +76,8 @@ class Case:
             s.set_tiling(*self.tiling)
         if self.lambda_fs is not None:
             s.set_solvation_lambda(self.lambda_fs)
+        if self.mrt is not None:
+            s.set_mrt(self.mrt)
         return s
 
 

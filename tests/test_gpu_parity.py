@@ -223,3 +223,52 @@ def test_invariant_with_fluid_solvation_on_gpu():
         assert np.abs(inv - inv0).max() < 1e-12, (k, inv - inv0)
     x, v, F, Fc = g.particles()
     assert np.abs(Fc).max() > 0
+
+
+MRT = (-1.3, -0.8, -1.1, -1.6)  # bulk, shear, momentum, kinetic eigenvalues
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-11), (FP32, 1e-5)])
+def test_mrt_with_particles(precision, tol):
+    """Distinct eigenvalues for the four mode groups, the general forcing
+    source term, particles with kappa and lambda solvation: 5 steps."""
+    c = Case((30, 20, 14), precision, PAPER, lbmd.KERNEL_AUTO, G=1.3, gamma=0.6, npart=40, vel_amp=0.03,
+             kappa=((0.2, -0.1),), mass=(20.0,), lambda_fs=((0.05, -0.02),), mrt=MRT)
+    g, o = run_pair(c, 5)
+    assert g.organisation() == TWOPASS
+    compare(c, g, o, tol * 5, tol * 5, "mrt")
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-11), (FP32, 1e-5)])
+def test_mrt_fluctuating_identical_draws(precision, tol):
+    """kT > 0 under MRT: each mode's noise amplitude follows its own
+    eigenvalue; the same Philox draws on both sides."""
+    c = Case((20, 18, 16), precision, PAPER, lbmd.KERNEL_AUTO, G=1.2, gamma=1.0, kT=1e-4, seed=11, npart=30,
+             kappa=((0.1, 0.0),), mass=(5.0,), mrt=MRT)
+    g, o = run_pair(c, 3)
+    compare(c, g, o, tol * 10, tol * 10, "mrt noise")
+
+
+def test_mrt_reduces_to_bgk():
+    """All four eigenvalues -1/tau give the BGK step (up to rounding)."""
+    tau = 0.8
+    c1 = Case((18, 14, 12), FP64, PAPER, TWOPASS, G=1.3, tau=tau, gamma=0.5, npart=20, vel_amp=0.02,
+              kappa=((0.2, -0.1),), mass=(5.0,), mrt=(-1 / tau,) * 4)
+    c0 = Case((18, 14, 12), FP64, PAPER, TWOPASS, G=1.3, tau=tau, gamma=0.5, npart=20, vel_amp=0.02,
+              kappa=((0.2, -0.1),), mass=(5.0,))
+    a, b = c1.gpu_sim(), c0.gpu_sim()
+    a.step(6)
+    b.step(6)
+    pa, pb = a.populations(), b.populations()
+    assert np.max(np.abs(pa - pb) / np.abs(pb)) < 1e-13
+
+
+def test_mrt_rejects_bad_eigenvalues():
+    s = lbmd.Sim((8, 8, 8))
+    with pytest.raises(lbmd.LbmdError):
+        s.set_mrt((-1.0, 0.1, -1.0, -1.0))
+    with pytest.raises(lbmd.LbmdError):
+        s.set_mrt((-2.0, -1.0, -1.0, -1.0))
+    f = lbmd.Sim((8, 8, 8), kernel=FUSED)
+    with pytest.raises(lbmd.LbmdError):
+        f.set_mrt(MRT)
