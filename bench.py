@@ -253,7 +253,9 @@ def main():
     ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("TILE_Y", "TILE_Z"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="advance the timed steps by replaying captured HIP graphs")
-    ap.add_argument("--autotune", action="store_true", help="pick the tiling with the library's autotuner first")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the library's default tiling instead of running its autotuner before the "
+                         "untimed warm-up")
     ap.add_argument("--serve-jobs", type=int, default=512, help="jobs in the served Poisson stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=32)

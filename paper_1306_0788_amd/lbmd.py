@@ -59,6 +59,14 @@ def load():
     if not os.path.exists(LIBPATH):
         raise RuntimeError("liblbmd.so is not built: run `python -m paper_1306_0788_amd.build` "
                            "(there is no fallback path)")
+    # torch ships its own HIP runtime under the same soname as the system one
+    # liblbmd.so links (libamdhip64.so.7); whichever is loaded first serves
+    # the whole process, and torch fails on a runtime other than its own.
+    # Loading torch first makes both use torch's.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIBPATH)
     H = ctypes.c_void_p
     L.lbmd_create.argtypes = [ctypes.POINTER(Params), _D, ctypes.c_void_p, ctypes.POINTER(H)]
