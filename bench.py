@@ -256,6 +256,9 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the library's default tiling instead of running its autotuner before the "
                          "untimed warm-up")
+    ap.add_argument("--autotune-cache", default=None, metavar="PATH",
+                    help="tiling cache file: a run that finds its key there skips the timing (profiling runs use "
+                         "the tiling an earlier run chose, without the candidates' launches in their traces)")
     ap.add_argument("--serve-jobs", type=int, default=512, help="jobs in the served Poisson stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=32)
@@ -316,7 +319,7 @@ def main():
     tuned = None
     if args.autotune:
         print("bench: autotuning the tiling", file=sys.stderr, flush=True)
-        tuned = sim.autotune(reps=3)
+        tuned = sim.autotune(reps=3, cache_path=args.autotune_cache)
     if args.graph:
         sim.set_graph(True)
     N = int(np.prod(w["shape"]))
@@ -362,6 +365,9 @@ def main():
     achieved = alg_bytes / kavg_s / 1e9
     kname = "k_fused" if sim_org == lbmd.KERNEL_FUSED else "k_collide"
     traffic = measured_traffic(kname, label)
+    # the same bytes moved by a pass with no arithmetic (one site per
+    # thread): what this access pattern reaches on the device
+    ceil_gbs = alg_bytes / (sim.stream_ceiling(10) * 1e-3) / 1e9
     line = {
         "metric": "MLUPS (2-component D3Q19 Shan-Chen + coupled particles, one full step)",
         "value": round(mlups, 2),
@@ -385,7 +391,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kname,
-                     "kernel_ms_avg": round(kavg_s * 1e3, 5), "bytes_per_site": 76 * s_bytes},
+                     "kernel_ms_avg": round(kavg_s * 1e3, 5), "bytes_per_site": 76 * s_bytes,
+                     "pattern_ceiling": round(ceil_gbs, 1), "frac_of_pattern_ceiling": round(achieved / ceil_gbs, 4)},
     }
     sim.close()
     del sim

@@ -254,6 +254,15 @@ int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z, int32_t flags
    number.  Waits.  Errors: LBMD_EDEVICE. */
 int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t* launches);
 
+/* Memory ceiling of the collide-stream access pattern: times reps launches
+   of a pass that reads every site's 38 pulled populations (in the handle's
+   storage type) and writes them unchanged, with no arithmetic, one site per
+   thread; *ms receives the average duration of one pass.  Only the scratch
+   population buffer (the destination of the next step) is written: the
+   state is unchanged.  Waits.  Errors: LBMD_EINVAL (reps < 1, NULL ms),
+   LBMD_ESTATE (attached to a batch), LBMD_EDEVICE. */
+int lbmd_stream_ceiling(lbmd_handle h, int32_t reps, double* ms);
+
 /* Organisation the next step will use: LBMD_KERNEL_FUSED or
    LBMD_KERNEL_TWOPASS (resolves LBMD_KERNEL_AUTO); negative on a NULL
    handle. */

@@ -816,6 +816,27 @@ int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t*
   return LBMD_OK;
 }
 
+int lbmd_stream_ceiling(lbmd_handle h, int32_t reps, double* ms) {
+  if (!h || reps < 1 || !ms) return fail(h, LBMD_EINVAL, "stream_ceiling: bad arguments");
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  HIPCHECK(h, fluid_pull_copy(h));  // first touch outside the timing
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHECK(h, hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = fluid_pull_copy(h);
+  if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(h, e, "stream_ceiling");
+  *ms = double(t) / reps;
+  return LBMD_OK;
+}
+
 int lbmd_set_graph(lbmd_handle h, int32_t enable) {
   if (!h) return LBMD_EINVAL;
   if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");

@@ -102,10 +102,10 @@ __device__ __forceinline__ void put_pop(const Pops<S>& p, int c, uint32_t vo, in
   }
 }
 
-// pulled populations of site (x,y,z): f_i(s) = src[i][s - c_i]
-template <class S, class C>
-__device__ __forceinline__ void pull(const Pops<S>& src, int x, int y, int z, int nx, int ny, int nz,
-                                     C (&f)[2][19]) {
+// fn(i, vo) for the 19 velocities of site (x,y,z), vo = byte offset of the
+// upstream site s - c_i (periodic)
+template <class S, class Fn>
+__device__ __forceinline__ void for_pulled(int x, int y, int z, int nx, int ny, int nz, Fn&& fn) {
   const uint32_t xm = wrapi(x - 1, nx), xp = wrapi(x + 1, nx), x0 = x;
   const uint32_t plane = uint32_t(nx) * uint32_t(ny);
   const uint32_t ym = wrapi(y - 1, ny) * nx, yp = wrapi(y + 1, ny) * nx, y0 = uint32_t(y) * nx;
@@ -115,17 +115,25 @@ __device__ __forceinline__ void pull(const Pops<S>& src, int x, int y, int z, in
     const uint32_t sx = D3Q19::cx[i] > 0 ? xm : (D3Q19::cx[i] < 0 ? xp : x0);
     const uint32_t sy = D3Q19::cy[i] > 0 ? ym : (D3Q19::cy[i] < 0 ? yp : y0);
     const uint32_t sz = D3Q19::cz[i] > 0 ? zm : (D3Q19::cz[i] < 0 ? zp : z0);
-    const uint32_t vo = (sz + sy + sx) * uint32_t(sizeof(S));
+    fn(i, (sz + sy + sx) * uint32_t(sizeof(S)));
+  }
+}
+
+// pulled populations of site (x,y,z): f_i(s) = src[i][s - c_i]
+template <class S, class C>
+__device__ __forceinline__ void pull(const Pops<S>& src, int x, int y, int z, int nx, int ny, int nz,
+                                     C (&f)[2][19]) {
+  for_pulled<S>(x, y, z, nx, ny, nz, [&](int i, uint32_t vo) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) f[c][i] = C(load_pop(src, c, vo, i));
-  }
+  });
 }
 
 // Stores the 38 post-collision populations of site s.  Deviation storage
 // draws 32 random bits per velocity (16 per component) from the site, the
 // velocity and the step key: the same on every tiling and every run.
-template <class S, class C>
-__device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&f)[2][19], bool nt = true) {
+template <int AUX, class S, class C>
+__device__ __forceinline__ void store_aux(const Pops<S>& dst, uint32_t s, const C (&f)[2][19]) {
   const uint32_t vo = s * uint32_t(sizeof(S));
   uint32_t hs = 0;
   if constexpr (Storage<S>::deviation) hs = mix32(s ^ dst.srkey);
@@ -133,14 +141,16 @@ __device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&
   for (int i = 0; i < 19; ++i) {
     uint32_t r = 0;
     if constexpr (Storage<S>::deviation) r = mix32(hs + uint32_t(i) * 0x9E3779B9u);
-    if (nt) {
-      put_pop<2>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
-      put_pop<2>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
-    } else {
-      put_pop<0>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
-      put_pop<0>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
-    }
+    put_pop<AUX>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
+    put_pop<AUX>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
   }
+}
+template <class S, class C>
+__device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&f)[2][19], bool nt = true) {
+  if (nt)
+    store_aux<2>(dst, s, f);
+  else
+    store_aux<0>(dst, s, f);
 }
 
 __device__ __forceinline__ void flag_unstable(uint32_t* status, long long* bad, uint32_t bit, long long step) {
@@ -795,6 +805,36 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
   }
 }
 
+// The collide-stream pass's memory traffic without its arithmetic: every
+// site's 38 pulled population words are read (src[i][s - c_i]) and written
+// unchanged to dst[i][s] (non-temporal), one site per thread.  Timing it
+// gives the bandwidth this access pattern reaches on the device, the
+// practical ceiling of the collide-stream kernels.
+template <class S>
+__global__ __launch_bounds__(256) void k_pull_copy(const S* __restrict__ src_, S* __restrict__ dst_, int nx, int ny,
+                                                   int nz, int64_t N) {
+  const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (s >= N) return;
+  const int x = int(s % nx), y = int((s / nx) % ny), z = int(s / (int64_t(nx) * ny));
+  const Pops<S> src = make_pops(src_, N), dst = make_pops(dst_, N);
+  const uint32_t vs = uint32_t(s) * uint32_t(sizeof(S));
+  for_pulled<S>(x, y, z, nx, ny, nz, [&](int i, uint32_t vo) {
+    const int so = int(uint32_t(i) * src.pstride);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if constexpr (sizeof(S) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_amdgcn_raw_buffer_load_b64(src.r[c], int(vo), so, 0), dst.r[c],
+                                              int(vs), so, 2);
+      else if constexpr (sizeof(S) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_raw_buffer_load_b32(src.r[c], int(vo), so, 0), dst.r[c],
+                                              int(vs), so, 2);
+      else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_amdgcn_raw_buffer_load_b16(src.r[c], int(vo), so, 0), dst.r[c],
+                                              int(vs), so, 2);
+    }
+  });
+}
+
 // final reductions: fluid partials [nf][5], particle partials [np][3] -> out[8]
 __device__ __forceinline__ void finalize_sums(const double* __restrict__ rf, int64_t nf, const double* __restrict__ rp,
                                               int64_t npb, double* __restrict__ out, int32_t* nflag, int64_t* step) {
@@ -893,6 +933,15 @@ static hipError_t export_t(lbmd_ctx* h, uint32_t mask, double* out) {
   return hipGetLastError();
 }
 hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out) { LBMD_BY_STORAGE(export_t, h, mask, out) }
+
+template <class S>
+static hipError_t pull_copy_t(lbmd_ctx* h) {
+  const int64_t N = h->N;
+  hipLaunchKernelGGL(k_pull_copy<S>, dim3((N + 255) / 256), dim3(256), 0, h->stream, (const S*)h->f[h->cur],
+                     (S*)h->f[1 - h->cur], h->p.nx, h->p.ny, h->p.nz, N);
+  return hipGetLastError();
+}
+hipError_t fluid_pull_copy(lbmd_ctx* h) { LBMD_BY_STORAGE(pull_copy_t, h) }
 
 // organisation actually used this step
 static int organisation(const lbmd_ctx* h) {

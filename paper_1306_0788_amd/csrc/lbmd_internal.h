@@ -387,6 +387,7 @@ hipError_t prof_end(lbmd_ctx* h);
 hipError_t fluid_init(lbmd_ctx* h, const double* rho_dev);
 hipError_t fluid_import(lbmd_ctx* h, const double* pop_dev);
 hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out_dev);
+hipError_t fluid_pull_copy(lbmd_ctx* h);
 hipError_t fluid_pass_a(lbmd_ctx* h);  // moments, SC force, records (+ fused collide)
 hipError_t fluid_pass_b(lbmd_ctx* h);  // collision with the particle force
 hipError_t finalize_step(lbmd_ctx* h);  // reductions, counters

@@ -372,24 +372,34 @@ __global__ __launch_bounds__(256) void k_couple(PartArgs A, const double* __rest
                 int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
 }
 
+// Second half kick.  Fcons (may be null): the conservative forces, added
+// here to the coupling force so that the pair forces can run beside the
+// fluid passes; F then holds the total force for the next step's kick.
 __device__ __forceinline__ void end_one(PartArgs A, const double* __restrict__ x, double* __restrict__ v,
-                                        const double* __restrict__ F, const int32_t* __restrict__ type,
-                                        uint32_t* status, long long* bad, int64_t p) {
+                                        double* __restrict__ F, const double* __restrict__ Fcons,
+                                        const int32_t* __restrict__ type, uint32_t* status, long long* bad,
+                                        int64_t p) {
   if (p >= A.np) return;
   A.step = *A.stepp;
   const double m = A.T.mass[type[p]];
   bool ok = true;
   for (int a = 0; a < 3; ++a) {
-    const double vn = v[3 * p + a] + 0.5 * F[3 * p + a] / m;
+    double Ft = F[3 * p + a];
+    if (Fcons) {
+      Ft += Fcons[3 * p + a];
+      F[3 * p + a] = Ft;
+    }
+    const double vn = v[3 * p + a] + 0.5 * Ft / m;
     v[3 * p + a] = vn;
-    ok = ok && isfinite(vn) && isfinite(x[3 * p + a]);
+    ok = ok && isfinite(Ft) && isfinite(vn) && isfinite(x[3 * p + a]);
   }
   if (!ok) flag_unstable(status, bad, 2u, A.step);
 }
 
-__global__ void k_end(PartArgs A, const double* __restrict__ x, double* __restrict__ v, const double* __restrict__ F,
-                      const int32_t* __restrict__ type, uint32_t* status, long long* bad) {
-  end_one(A, x, v, F, type, status, bad, int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+__global__ void k_end(PartArgs A, const double* __restrict__ x, double* __restrict__ v, double* __restrict__ F,
+                      const double* __restrict__ Fcons, const int32_t* __restrict__ type, uint32_t* status,
+                      long long* bad) {
+  end_one(A, x, v, F, Fcons, type, status, bad, int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------ launchers
@@ -439,10 +449,12 @@ bool has_conservative(const lbmd_ctx* h) {
 
 // Conservative forces on the side stream, ordered after the kick/drift/cell
 // sort on the main stream (particles_mark_sorted records that point); the
-// main stream waits for them before coupling.  The density pass is enqueued
-// between the two calls, so it is dispatched first and gets the whole chip
-// in its first wave of blocks, with the pair forces filling in beside it
-// (also in a captured graph, whose nodes follow the enqueue order).
+// main stream waits for them only before the second half kick, so they run
+// beside the density pass, the coupling and the collide pass.  The density
+// pass is enqueued between the two calls, so it is dispatched first and
+// gets the whole chip in its first wave of blocks, with the pair forces
+// filling in beside it (also in a captured graph, whose nodes follow the
+// enqueue order).
 hipError_t particles_mark_sorted(lbmd_ctx* h) {
   if (!has_conservative(h)) return hipSuccess;
   return hipEventRecord(h->ev_sorted, h->stream);
@@ -460,11 +472,8 @@ hipError_t particles_pairs(lbmd_ctx* h) {
 
 hipError_t particles_forces(lbmd_ctx* h) {
   PartArgs A = args(h);
-  const bool cons = has_conservative(h);
-  if (cons)
-    if (hipError_t e = hipStreamWaitEvent(h->stream, h->ev_pairs, 0)) return e;
   const int64_t nb = (h->np + 255) / 256;
-  const double* Fcons = cons ? h->Fcons : nullptr;
+  const double* Fcons = nullptr;  // added by the second half kick
   if (h->p.precision == LBMD_FP64)
     hipLaunchKernelGGL(k_couple<double>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, Fcons,
                        h->type, (const double*)h->rec, (double*)h->gP, (double*)h->gS, h->cell_perm, h->status,
@@ -478,8 +487,11 @@ hipError_t particles_forces(lbmd_ctx* h) {
 
 hipError_t particles_end(lbmd_ctx* h) {
   PartArgs A = args(h);
-  hipLaunchKernelGGL(k_end, dim3((h->np + 255) / 256), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->type,
-                     h->status, h->bad_step);
+  const bool cons = has_conservative(h);
+  if (cons)
+    if (hipError_t e = hipStreamWaitEvent(h->stream, h->ev_pairs, 0)) return e;
+  hipLaunchKernelGGL(k_end, dim3((h->np + 255) / 256), dim3(256), 0, h->stream, A, h->x, h->v, h->F,
+                     cons ? (const double*)h->Fcons : nullptr, h->type, h->status, h->bad_step);
   return hipGetLastError();
 }
 
@@ -536,7 +548,7 @@ __global__ __launch_bounds__(256) void k_end_batch(const BatchJob* __restrict__ 
   for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
     const BatchJob& J = jobs[batch_job_of<&BatchJob::pblk_begin>(jobs, nj, u)];
     if (!batch_active(J)) continue;
-    end_one(J.A, J.x, J.v, J.F, J.type, J.status, J.bad, (u - J.pblk_begin) * 256 + threadIdx.x);
+    end_one(J.A, J.x, J.v, J.F, nullptr, J.type, J.status, J.bad, (u - J.pblk_begin) * 256 + threadIdx.x);
   }
 }
 

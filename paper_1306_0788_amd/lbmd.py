@@ -26,7 +26,7 @@ EXPORTS = ["lbmd_create", "lbmd_destroy", "lbmd_set_particles", "lbmd_set_partic
            "lbmd_last_error", "lbmd_set_tiling", "lbmd_kernel_timing", "lbmd_organisation", "lbmd_set_graph",
            "lbmd_autotune", "lbmd_batch_create", "lbmd_batch_destroy", "lbmd_batch_attach", "lbmd_batch_detach",
            "lbmd_batch_step", "lbmd_batch_poll", "lbmd_batch_last_error", "lbmd_set_solvation_lambda",
-           "lbmd_set_mrt"]
+           "lbmd_set_mrt", "lbmd_stream_ceiling"]
 
 
 class LbmdError(RuntimeError):
@@ -90,6 +90,7 @@ def load():
     L.lbmd_set_tiling.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.lbmd_kernel_timing.argtypes = [H, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64)]
     L.lbmd_organisation.argtypes = [H]
+    L.lbmd_stream_ceiling.argtypes = [H, ctypes.c_int32, _D]
     L.lbmd_set_graph.argtypes = [H, ctypes.c_int32]
     L.lbmd_autotune.argtypes = [H, ctypes.c_int32, ctypes.c_char_p, _I32, _D]
     L.lbmd_batch_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(H)]
@@ -263,6 +264,13 @@ class Sim:
         n = ctypes.c_int64()
         self._check(load().lbmd_kernel_timing(self._h, int(enable), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def stream_ceiling(self, reps=10):
+        """Average ms of one pass that moves the collide-stream kernel's bytes
+        (38 pulled loads and 38 stores per site) with no arithmetic."""
+        ms = ctypes.c_double()
+        self._check(load().lbmd_stream_ceiling(self._h, int(reps), ctypes.byref(ms)))
+        return ms.value
 
     def set_graph(self, enable=True):
         """Advance steps two at a time by replaying captured HIP graphs."""

@@ -94,3 +94,23 @@ def test_autotune_leaves_state_and_results_unchanged(kernel):
     assert a.sync() == lbmd.OK
     # five FP32 steps: the one-step FP32 bound (1e-5) times the step count
     compare(c, a, o, 5e-5, 5e-5, "after autotune")
+
+
+@pytest.mark.parametrize("precision", [lbmd.FP64, lbmd.FP32, lbmd.BF16DEV])
+def test_stream_ceiling_leaves_state_unchanged(precision):
+    """The pattern-ceiling pass writes only the scratch buffer: populations,
+    step index and the next steps are those of a handle that never ran it."""
+    # no particles: no float atomics, so two handles agree bit for bit
+    c = Case((70, 33, 21), precision, lbmd.FORCE_PAPER, lbmd.KERNEL_TWOPASS, G=1.3, npart=0)
+    print("stream ceiling precision=%d" % precision, flush=True)
+    a, b = c.gpu_sim(), c.gpu_sim()
+    a.step(2)
+    b.step(2)
+    before = a.populations()
+    ms = a.stream_ceiling(3)
+    assert ms > 0
+    assert np.array_equal(a.populations(), before) and a.step_index == 2
+    a.step(3)
+    b.step(3)
+    assert a.sync() == lbmd.OK and b.sync() == lbmd.OK
+    assert np.array_equal(a.populations(), b.populations())
