@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "lbmd_internal.h"
 #include "lbmd_site.h"
@@ -132,25 +133,43 @@ __device__ __forceinline__ void pull(const Pops<S>& src, int x, int y, int z, in
 // Stores the 38 post-collision populations of site s.  Deviation storage
 // draws 32 random bits per velocity (16 per component) from the site, the
 // velocity and the step key: the same on every tiling and every run.
-template <int AUX, class S, class C>
-__device__ __forceinline__ void store_aux(const Pops<S>& dst, uint32_t s, const C (&f)[2][19]) {
+// SPLIT: one branch on the store hint for the whole site; otherwise one per
+// velocity, which keeps each pair's stores next to its arithmetic (measured
+// faster for the deterministic FP32/FP64 collision, slower with the noise
+// or the 16-bit encoding, whose extra arithmetic then sits between stores).
+template <class S, class C, bool SPLIT = false>
+__device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&f)[2][19], bool nt = true) {
   const uint32_t vo = s * uint32_t(sizeof(S));
   uint32_t hs = 0;
   if constexpr (Storage<S>::deviation) hs = mix32(s ^ dst.srkey);
+  auto put_all = [&](auto aux) {
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    uint32_t r = 0;
-    if constexpr (Storage<S>::deviation) r = mix32(hs + uint32_t(i) * 0x9E3779B9u);
-    put_pop<AUX>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
-    put_pop<AUX>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
+    for (int i = 0; i < 19; ++i) {
+      uint32_t r = 0;
+      if constexpr (Storage<S>::deviation) r = mix32(hs + uint32_t(i) * 0x9E3779B9u);
+      put_pop<decltype(aux)::value>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
+      put_pop<decltype(aux)::value>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
+    }
+  };
+  if constexpr (SPLIT) {
+    if (nt)
+      put_all(std::integral_constant<int, 2>());
+    else
+      put_all(std::integral_constant<int, 0>());
+  } else {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      uint32_t r = 0;
+      if constexpr (Storage<S>::deviation) r = mix32(hs + uint32_t(i) * 0x9E3779B9u);
+      if (nt) {
+        put_pop<2>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
+        put_pop<2>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
+      } else {
+        put_pop<0>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
+        put_pop<0>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
+      }
+    }
   }
-}
-template <class S, class C>
-__device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&f)[2][19], bool nt = true) {
-  if (nt)
-    store_aux<2>(dst, s, f);
-  else
-    store_aux<0>(dst, s, f);
 }
 
 __device__ __forceinline__ void flag_unstable(uint32_t* status, long long* bad, uint32_t bit, long long step) {
@@ -799,7 +818,7 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
       }
       const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K, fs ? gu : nullptr);
       relax_site<C, FORCING, NOISE, MRT>(f, m, K, uint32_t(s));
-      store<S, C>(dst, uint32_t(s), f, K.nt);
+      store<S, C, NOISE || Storage<S>::deviation>(dst, uint32_t(s), f, K.nt);
     }
     if (z + 2 <= z1) load_border(z + 2, (k + 3) & 3);
   }
@@ -960,10 +979,11 @@ struct Launch {
 // Tiling actually launched: the caller's (lbmd_set_tiling or
 // lbmd_autotune), else defaults from measurements on MI355X: the fused
 // kernel with 4 rows and its populations held in registers, the two-pass
-// kernels with 8 rows in XCD order; the z chunk is chosen so that a launch
-// has about 256 blocks (16 and 128 planes at 256^3, the measured optima),
-// within [2, 16] planes for the fused kernel and [4, 128] for the two-pass
-// kernels.  Rows never exceed the lattice height.
+// kernels with 8 rows (16 on 16-bit storage or with noise) in XCD order; the z chunk is
+// chosen so that a launch has about 256 blocks (16, 128 and 64 planes at
+// 256^3, the measured optima), within [2, 16] planes for the fused kernel
+// and [4, 128] for the two-pass kernels.  Rows never exceed the lattice
+// height.
 static int pow2_floor(int64_t v) {
   int p = 1;
   while (int64_t(p) * 2 <= v) p *= 2;
@@ -972,7 +992,10 @@ static int pow2_floor(int64_t v) {
 static Launch tiles(lbmd_ctx* h) {
   if (!h->tiling_set) {
     const bool fused = organisation_of(h) == LBMD_KERNEL_FUSED;
-    const int want = fused ? 4 : 8;
+    // rows: 16 for the two-pass kernels on 16-bit storage or with thermal
+    // noise, 8 otherwise
+    const bool wide = h->p.precision == LBMD_FP16DEV || h->p.precision == LBMD_BF16DEV || h->p.kT > 0.0;
+    const int want = fused ? 4 : (wide ? 16 : 8);
     int ty = 2;
     while (ty < want && ty * 2 <= h->p.ny) ty *= 2;
     const int64_t cols = int64_t((h->p.nx + 63) / 64) * ((h->p.ny + ty - 1) / ty);
