@@ -131,8 +131,10 @@ __device__ __forceinline__ void pull(const Pops<S>& src, int x, int y, int z, in
 }
 
 // Stores the 38 post-collision populations of site s.  Deviation storage
-// draws 32 random bits per velocity (16 per component) from the site, the
-// velocity and the step key: the same on every tiling and every run.
+// draws 32 random bits per velocity (16 per component): the site's word
+// mix32(s ^ step key) seeds a xorshift32 sequence whose i-th output serves
+// velocity i (cheap shift/xor steps instead of a multiplying hash per
+// value), the same on every tiling, organisation and run.
 // SPLIT: one branch on the store hint for the whole site; otherwise one per
 // velocity, which keeps each pair's stores next to its arithmetic (measured
 // faster for the deterministic FP32/FP64 collision, slower with the noise
@@ -141,12 +143,15 @@ template <class S, class C, bool SPLIT = false>
 __device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&f)[2][19], bool nt = true) {
   const uint32_t vo = s * uint32_t(sizeof(S));
   uint32_t hs = 0;
-  if constexpr (Storage<S>::deviation) hs = mix32(s ^ dst.srkey);
+  if constexpr (Storage<S>::deviation) {
+    hs = mix32(s ^ dst.srkey);
+    if (hs == 0u) hs = 0x9E3779B9u;  // xorshift32 needs a nonzero seed
+  }
   auto put_all = [&](auto aux) {
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
       uint32_t r = 0;
-      if constexpr (Storage<S>::deviation) r = mix32(hs + uint32_t(i) * 0x9E3779B9u);
+      if constexpr (Storage<S>::deviation) r = hs = xorshift32(hs);
       put_pop<decltype(aux)::value>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
       put_pop<decltype(aux)::value>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);
     }
@@ -160,7 +165,7 @@ __device__ __forceinline__ void store(const Pops<S>& dst, uint32_t s, const C (&
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
       uint32_t r = 0;
-      if constexpr (Storage<S>::deviation) r = mix32(hs + uint32_t(i) * 0x9E3779B9u);
+      if constexpr (Storage<S>::deviation) r = hs = xorshift32(hs);
       if (nt) {
         put_pop<2>(dst, 0, vo, i, arith_t<S>(f[0][i]), r);
         put_pop<2>(dst, 1, vo, i, arith_t<S>(f[1][i]), r >> 16);

@@ -76,6 +76,15 @@ __host__ __device__ constexpr uint32_t mix32(uint32_t x) {
   return x;
 }
 
+// xorshift32 (Marsaglia, "Xorshift RNGs", 2003): one step of the 13/17/5
+// shift triple, a bijection on the nonzero 32-bit words.
+__host__ __device__ constexpr uint32_t xorshift32(uint32_t x) {
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+
 // Stochastic rounding of a stored deviation: r (16 random bits) is added
 // below the kept mantissa bits of |v| and the rest truncated, so the stored
 // value rounds up with probability equal to the discarded fraction and is

@@ -205,16 +205,34 @@ __device__ __forceinline__ void add_radial(double fr, const double (&d)[3], doub
 // Conservative forces (pair potentials from the cell list, FENE bonds) at
 // the new positions; independent of the fluid, so it runs on a second stream
 // while the density pass streams the populations.
-__global__ __launch_bounds__(256) void k_pairs(PartArgs A, const double* __restrict__ x,
-                                               const int32_t* __restrict__ type,
-                                               const int32_t* __restrict__ cell_start,
-                                               const int32_t* __restrict__ perm, const int32_t* __restrict__ cell_of,
-                                               const int32_t* __restrict__ bstart, const int32_t* __restrict__ bnbr,
-                                               double* __restrict__ Fcons) {
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (tid >= A.np) return;
-  // particles in cell order: neighbouring threads share cells
-  const int64_t p = A.use_cells ? int64_t(perm[tid]) : tid;
+// sum over the 8 lanes of an aligned lane group, identical on every lane
+// (each butterfly level adds the same two values)
+__device__ __forceinline__ double group8_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Pair and bond forces with 8 lanes per particle: lane l takes the
+// neighbour cells (and bonds) whose running index is l mod 8, and the
+// group sums the 8 partial forces.  The particle's force is the same sum
+// of pair terms in another order.
+constexpr int PAIRS_BLOCK = 256;
+__global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double* __restrict__ x,
+                                                       const int32_t* __restrict__ type,
+                                                       const int32_t* __restrict__ cell_start,
+                                                       const int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ cell_of,
+                                                       const int32_t* __restrict__ bstart,
+                                                       const int32_t* __restrict__ bnbr, double* __restrict__ Fcons) {
+  const int64_t tid = int64_t(blockIdx.x) * (PAIRS_BLOCK / 8) + (threadIdx.x >> 3);
+  const int l = threadIdx.x & 7;
+  // every lane of a group takes part in the final sum; a group past the last
+  // particle works on the last one and writes nothing
+  const bool on = tid < A.np;
+  const int64_t tc = on ? tid : A.np - 1;
+  // particles in cell order: neighbouring groups share cells
+  const int64_t p = A.use_cells ? int64_t(perm[tc]) : tc;
   const int t = type[p];
   const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
   double Fp[3] = {0, 0, 0};
@@ -225,11 +243,13 @@ __global__ __launch_bounds__(256) void k_pairs(PartArgs A, const double* __restr
     const int lo[3] = {A.ncell[0] >= 3 ? -1 : 0, A.ncell[1] >= 3 ? -1 : 0, A.ncell[2] >= 3 ? -1 : 0};
     const int hi[3] = {A.ncell[0] >= 3 ? 1 : 0, A.ncell[1] >= 3 ? 1 : 0, A.ncell[2] >= 3 ? 1 : 0};
     const double qp = A.T.charge[t];
-    // all cell ranges first (independent loads), then the pairs
-    int rb[27], re[27], nr = 0;
+    // this lane's cell ranges first (independent loads), then the pairs
+    int rb[4], re[4], nr = 0;
+    int idx = 0;
     for (int dz = lo[2]; dz <= hi[2]; ++dz)
       for (int dy = lo[1]; dy <= hi[1]; ++dy)
-        for (int dx = lo[0]; dx <= hi[0]; ++dx) {
+        for (int dx = lo[0]; dx <= hi[0]; ++dx, ++idx) {
+          if ((idx & 7) != l) continue;
           const int nc = (wrapi(cz + dz, A.ncell[2]) * A.ncell[1] + wrapi(cy + dy, A.ncell[1])) * A.ncell[0] +
                          wrapi(cx + dx, A.ncell[0]);
           rb[nr] = cell_start[nc];
@@ -257,7 +277,7 @@ __global__ __launch_bounds__(256) void k_pairs(PartArgs A, const double* __restr
     }
   }
   if (A.pp.fene_on && bstart) {
-    for (int jj = bstart[p]; jj < bstart[p + 1]; ++jj) {
+    for (int jj = bstart[p] + l; jj < bstart[p + 1]; jj += 8) {
       const int q = bnbr[jj];
       double d[3];
       for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
@@ -267,7 +287,10 @@ __global__ __launch_bounds__(256) void k_pairs(PartArgs A, const double* __restr
       add_radial(fr, d, r, Fp);
     }
   }
-  for (int a = 0; a < 3; ++a) Fcons[3 * p + a] = Fp[a];
+  for (int a = 0; a < 3; ++a) {
+    const double Fa = group8_sum(Fp[a]);
+    if (on && l == 0) Fcons[3 * p + a] = Fa;
+  }
 }
 
 // Coupling force: trilinear interpolation of u_c and the lattice density
@@ -361,15 +384,95 @@ __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict_
     for (int a = 0; a < 3; ++a) atomicAdd(&gP[node[k] * 4 + a], C(-W[k] * fc[a]));
 }
 
+
+// Coupling with 8 lanes per particle (single-job path): lane k owns node k
+// of the particle's cell, gathers that node's record, and the 8 partial
+// sums are combined with a butterfly of shuffles inside the lane group
+// (identical on every lane: each level adds the same two values); every
+// lane then has the interpolated u and grad rho, lane 0 writes the forces,
+// and each lane spreads onto its own node.  Eight times the parallelism of
+// one thread per particle for the scattered record loads and the atomics.
+// Same arithmetic as couple_one, with the 8-term sums in tree order.
+constexpr int COUPLE8_BLOCK = 256;
 template <class C>
-__global__ __launch_bounds__(256) void k_couple(PartArgs A, const double* __restrict__ x,
-                                                const double* __restrict__ v, double* __restrict__ F,
-                                                double* __restrict__ Fc, const double* __restrict__ Fcons,
-                                                const int32_t* __restrict__ type, const C* __restrict__ rec,
-                                                C* __restrict__ gP, C* __restrict__ gS, const int32_t* __restrict__ perm,
-                                                uint32_t* status, long long* bad) {
-  couple_one<C>(A, x, v, F, Fc, Fcons, type, rec, gP, gS, perm, status, bad,
-                int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const double* __restrict__ x,
+                                                           const double* __restrict__ v, double* __restrict__ F,
+                                                           double* __restrict__ Fc, const int32_t* __restrict__ type,
+                                                           const C* __restrict__ rec, C* __restrict__ gP,
+                                                           C* __restrict__ gS, const int32_t* __restrict__ perm,
+                                                           uint32_t* status, long long* bad) {
+  const int64_t tid = int64_t(blockIdx.x) * (COUPLE8_BLOCK / 8) + (threadIdx.x >> 3);
+  const int k = threadIdx.x & 7;
+  // every lane of a group takes part in the shuffles; a group past the last
+  // particle works on the last one and writes nothing
+  const bool on = tid < A.np;
+  const int64_t tc = on ? tid : A.np - 1;
+  A.step = *A.stepp;
+  const int64_t p = A.use_cells ? int64_t(perm[tc]) : tc;
+  const int t = type[p];
+  const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
+  const double fl[3] = {floor(xp[0]), floor(xp[1]), floor(xp[2])};
+  const double d[3] = {xp[0] - fl[0], xp[1] - fl[1], xp[2] - fl[2]};
+  const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
+  const double Wk = (ox ? d[0] : 1.0 - d[0]) * (oy ? d[1] : 1.0 - d[1]) * (oz ? d[2] : 1.0 - d[2]);
+  const int64_t nk = (int64_t(wrapi(cell_coord(fl[2], A.nz) + oz, A.nz)) * A.ny +
+                      wrapi(cell_coord(fl[1], A.ny) + oy, A.ny)) * A.nx +
+                     wrapi(cell_coord(fl[0], A.nx) + ox, A.nx);
+  const C* r = rec + nk * 16;
+  double gA[3], gB[3], up[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gA[a] = group8_sum(Wk * 3.0 * double(r[a]));
+    gB[a] = group8_sum(Wk * 3.0 * double(r[3 + a]));
+    up[a] = group8_sum(Wk * double(r[6 + a]));
+  }
+  double R[4] = {0, 0, 0, 0};
+  if (A.kT > 0.0) {
+    normals4<double>(A.seed, A.step, uint32_t(p), 0u, 1u, R);
+    const double amp = sqrt(2.0 * A.kT * A.gamma);
+    for (int a = 0; a < 3; ++a) R[a] *= amp;
+  }
+  double back[3] = {0, 0, 0};
+  if (gS && (A.T.lambda[t][0] != 0.0 || A.T.lambda[t][1] != 0.0)) {
+    // fluid solvation force at this lane's vertex (as solvation_lambda)
+    const double la = A.T.lambda[t][0], lb = A.T.lambda[t][1];
+    const double dv[3] = {xp[0] - (fl[0] + ox), xp[1] - (fl[1] + oy), xp[2] - (fl[2] + oz)};
+    double S[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
+      const double dot = dv[0] * cx + dv[1] * cy + dv[2] * cz;
+      const double wgt = (cx * cx + cy * cy + cz * cz) == 1 ? 1.0 : 0.5;
+      if (dot > 0.0) {
+        S[0] += wgt * cx;
+        S[1] += wgt * cy;
+        S[2] += wgt * cz;
+      }
+    }
+    const double ra = double(r[9]), rb = double(r[10]);
+    for (int a = 0; a < 3; ++a) {
+      if (on) {
+        atomicAdd(&gS[nk * 8 + a], C(la * S[a]));
+        atomicAdd(&gS[nk * 8 + 3 + a], C(lb * S[a]));
+      }
+      back[a] = group8_sum((la * ra + lb * rb) * S[a]);
+    }
+  }
+  double fc[3];
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) {
+    fc[a] = -A.gamma * (v[3 * p + a] - up[a]) - (A.T.kappa[t][0] * gA[a] + A.T.kappa[t][1] * gB[a]) + R[a];
+    const double Ft = fc[a] + back[a] + 0.0;  // the pair forces are added by the second half kick
+    if (on && k == 0) {
+      Fc[3 * p + a] = fc[a] + back[a];
+      F[3 * p + a] = Ft;
+    }
+    ok = ok && isfinite(Ft);
+  }
+  if (on && k == 0 && !ok) flag_unstable(status, bad, 2u, A.step);
+  // the interpolated part goes back to the fluid by the same interpolation
+  if (on)
+    for (int a = 0; a < 3; ++a) atomicAdd(&gP[nk * 4 + a], C(-Wk * fc[a]));
 }
 
 // Second half kick.  Fcons (may be null): the conservative forces, added
@@ -464,22 +567,23 @@ hipError_t particles_pairs(lbmd_ctx* h) {
   if (!has_conservative(h)) return hipSuccess;
   PartArgs A = args(h);
   if (hipError_t e = hipStreamWaitEvent(h->side, h->ev_sorted, 0)) return e;
-  hipLaunchKernelGGL(k_pairs, dim3((h->np + 255) / 256), dim3(256), 0, h->side, A, h->x, h->type, h->cell_start,
-                     h->cell_perm, h->cell_of, h->bond_start, h->bond_nbr, h->Fcons);
+  const int64_t nb = (h->np + PAIRS_BLOCK / 8 - 1) / (PAIRS_BLOCK / 8);
+  hipLaunchKernelGGL(k_pairs, dim3(nb), dim3(PAIRS_BLOCK), 0, h->side, A, h->x, h->type, h->cell_start, h->cell_perm,
+                     h->cell_of, h->bond_start, h->bond_nbr, h->Fcons);
   if (hipError_t e = hipGetLastError()) return e;
   return hipEventRecord(h->ev_pairs, h->side);
 }
 
 hipError_t particles_forces(lbmd_ctx* h) {
   PartArgs A = args(h);
-  const int64_t nb = (h->np + 255) / 256;
-  const double* Fcons = nullptr;  // added by the second half kick
+  // pair forces: added by the second half kick
+  const int64_t nb = (h->np + COUPLE8_BLOCK / 8 - 1) / (COUPLE8_BLOCK / 8);
   if (h->p.precision == LBMD_FP64)
-    hipLaunchKernelGGL(k_couple<double>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, Fcons,
+    hipLaunchKernelGGL(k_couple8<double>, dim3(nb), dim3(COUPLE8_BLOCK), 0, h->stream, A, h->x, h->v, h->F, h->Fc,
                        h->type, (const double*)h->rec, (double*)h->gP, (double*)h->gS, h->cell_perm, h->status,
                        h->bad_step);
   else
-    hipLaunchKernelGGL(k_couple<float>, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, Fcons,
+    hipLaunchKernelGGL(k_couple8<float>, dim3(nb), dim3(COUPLE8_BLOCK), 0, h->stream, A, h->x, h->v, h->F, h->Fc,
                        h->type, (const float*)h->rec, (float*)h->gP, (float*)h->gS, h->cell_perm, h->status,
                        h->bad_step);
   return hipGetLastError();
