@@ -88,9 +88,10 @@ typedef struct lbmd_ctx* lbmd_handle;
                                  stream, then a sparse re-collision of the
                                  nodes the particles touch (best with few
                                  particles)                                   */
-#define LBMD_KERNEL_TWOPASS 1 /* a density pass (density field, records at the
-                                 touched nodes), then collide + stream with the
-                                 particle force applied in-line               */
+#define LBMD_KERNEL_TWOPASS 1 /* a streaming density pass (density field,
+                                 momentum at the touched nodes), then collide +
+                                 stream with the particle force applied
+                                 in-line                                      */
 #define LBMD_KERNEL_AUTO 2    /* fused with fewer than one touched node per 128
                                  sites, two-pass otherwise                    */
 

@@ -418,7 +418,9 @@ int lbmd_create(const lbmd_params* p, const double* rho_init, void* hip_stream, 
   // reduction partials: the largest launch is the two-row fused tiling with
   // one plane per block, or the two-pass collide grid
   const int64_t tiles_x = (p->nx + 63) / 64;
-  h->red_fluid_cap = std::max<int64_t>(tiles_x * ((p->ny + 1) / 2) * p->nz, tiles_x * ((p->ny + 3) / 4) * p->nz);
+  // partials of the tiled passes (at least 2 rows per tile) and of the flat
+  // density pass (512 sites per block)
+  h->red_fluid_cap = std::max<int64_t>(tiles_x * ((p->ny + 1) / 2) * p->nz, (h->N + 511) / 512);
   if (dalloc(&h->red_fluid, 5 * h->red_fluid_cap) != hipSuccess) return bail(LBMD_ENOMEM);
   if (dalloc(&h->red_out, 8) != hipSuccess || dalloc(&h->status, 1) != hipSuccess ||
       dalloc(&h->bad_step, 1) != hipSuccess || dalloc(&h->nflag, 1) != hipSuccess ||

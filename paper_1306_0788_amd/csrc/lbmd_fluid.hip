@@ -10,8 +10,10 @@
 // The Shan-Chen force at s needs the densities of the 18 neighbours
 // (Sec. 2, Eq. SCforce), each a sum of 19 pulled populations.  Two kernel
 // organisations are provided:
-//   two-pass  k_density writes rho[2][N]; k_collide reads it back as a
-//             stencil (118 values of traffic per site);
+//   two-pass  k_dens streams the pulled populations, one site per thread,
+//             and writes rho[2][N]; k_collide marches a tile along z with
+//             the densities staged in an LDS ring from that field, so the
+//             pass pair moves 38 + 38 + 38 values per site plus the field;
 //   fused     k_fused marches a 64 x TY tile along z, builds the density of
 //             each new plane (tile + one-site ring) into a 4-slot LDS ring,
 //             keeps the tile's own populations of the next plane in
@@ -21,7 +23,10 @@
 // particle force, which needs the node's u_c and grad rho of the same step.
 // The fused kernel therefore collides every site without it, stores u_c and
 // the neighbour sums at the touched nodes (records), and k_fix re-collides
-// only those nodes once the particle forces are spread.
+// only those nodes once the particle forces are spread.  In the two-pass
+// organisation the density pass stores the raw momentum and the densities
+// at the touched nodes, the coupling kernel forms the neighbour sums from
+// the density field, and the collide pass applies the spread force in-line.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -652,113 +657,63 @@ __global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __res
 }
 
 // ------------------------------------------------------------ split path
-// Pass P: density field, conservation sums, status, and the records at the
-// touched nodes (neighbour sums from the density ring, u_c).  No collision.
-template <class S, int TY, int FORCING>
-__global__ __launch_bounds__(64 * TY) void k_moments(const S* __restrict__ src_, arith_t<S>* __restrict__ rho,
-                                                      FluidConsts<arith_t<S>> K, int tz, int tiles_x, int xcd,
-                                                      const uint32_t* __restrict__ mask, arith_t<S>* __restrict__ rec,
-                                                      double* __restrict__ red, uint32_t* status, long long* bad) {
+// Pass P, flat: one site per thread per pass over the lattice (a grid of at
+// most DENS_GRID blocks strides through it, so the per-block FP64 partials
+// stay few for the final reduction), no tiling.  The density field, the
+// conservation sums and the status; at the nodes particles touch, the raw
+// momentum and the two densities go to the node record (the coupling kernel
+// forms the neighbour sums there from the density field).  A plain
+// streaming read of the 38 pulled populations per site.
+constexpr int DENS_BLOCK = 512, DENS_GRID = 2048;
+template <class S>
+__global__ __launch_bounds__(DENS_BLOCK) void k_dens(const S* __restrict__ src_, arith_t<S>* __restrict__ rho,
+                                                     FluidConsts<arith_t<S>> K, const uint32_t* __restrict__ mask,
+                                                     arith_t<S>* __restrict__ rec, double* __restrict__ red,
+                                                     uint32_t* status, long long* bad) {
   using C = arith_t<S>;
   load_step(K);
-  __shared__ C ring[4][2][TY + 2][66];
   const int nx = K.nx, ny = K.ny, nz = K.nz;
   const int64_t N = K.N;
-  const int64_t plane = int64_t(nx) * ny;
   const Pops<S> src = make_pops(src_, N, K.rho0);
-  const Tile<TY> T(nx, ny, nz, tz, tiles_x, xcd, blockIdx.x, gridDim.x);
-  const int lane = T.lane, wv = T.wv, x = T.x, y = T.y;
   double acc[5] = {0, 0, 0, 0, 0};
-  C jn[3] = {0, 0, 0}, jc[3] = {0, 0, 0};  // raw momentum of the next / current plane
-
-  auto load_interior = [&](int zp_raw, int slot) {
-    const int zz = wrapi(zp_raw, nz);
-    if (T.inside) {
-      C f[2][19];
-      pull<S, C>(src, x, y, zz, nx, ny, nz, f);
-      C jt[3] = {0, 0, 0};
+  for (int64_t s = int64_t(blockIdx.x) * DENS_BLOCK + threadIdx.x; s < N; s += int64_t(gridDim.x) * DENS_BLOCK) {
+    const int x = int(s % nx), y = int((s / nx) % ny), z = int(s / (int64_t(nx) * ny));
+    C f[2][19];
+    pull<S, C>(src, x, y, z, nx, ny, nz, f);
+    SiteOut<C> o;
+    C jt[3] = {0, 0, 0};
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        C r, jj[3];
-        moments_pairs<C>(f[c], r, jj);
-        ring[slot][c][wv + 1][lane + 1] = r;
+    for (int c = 0; c < 2; ++c) {
+      C jj[3];
+      moments_pairs<C>(f[c], o.rho[c], jj);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) jt[a] += jj[a];
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) jn[a] = jt[a];
+      for (int a = 0; a < 3; ++a) jt[a] += jj[a];
     }
-  };
-  auto load_border = [&](int zp_raw, int slot) {
-    const int zz = wrapi(zp_raw, nz);
-    T.for_border([&](int hr, int hc) {
-      C hf[2][19];
-      pull<S, C>(src, wrapi(T.x0 - 1 + hc, nx), wrapi(T.y0 - 1 + hr, ny), zz, nx, ny, nz, hf);
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        C r = hf[c][0];
-#pragma unroll
-        for (int i = 1; i < 19; ++i) r += hf[c][i];
-        ring[slot][c][hr][hc] = r;
-      }
-    });
-  };
-
-  const int z0 = T.z0, z1 = T.z1;
-  load_interior(z0 - 1, 0);
-  load_border(z0 - 1, 0);
-  load_interior(z0, 1);
-  load_border(z0, 1);
-  load_border(z0 + 1, 2);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) jc[a] = jn[a];
-  for (int z = z0; z < z1; ++z) {
-    const int k = z - z0;
-    load_interior(z + 1, (k + 2) & 3);
-    __syncthreads();
-    if (T.inside) {
-      const int s0 = (k + 1) & 3;
-      const int64_t s = z * plane + int64_t(y) * nx + x;
-      SiteOut<C> o;
-      o.rho[0] = ring[s0][0][wv + 1][lane + 1];
-      o.rho[1] = ring[s0][1][wv + 1][lane + 1];
-      o.j[0] = jc[0];
-      o.j[1] = jc[1];
-      o.j[2] = jc[2];
-      rho[s] = o.rho[0];
-      rho[N + s] = o.rho[1];
-      if (mask && ((mask[s >> 5] >> (s & 31)) & 1u)) {
-        C NA[3], NB[3];
-        nsum_ring<C, TY>(ring, k & 3, s0, (k + 2) & 3, wv, lane, NA, NB);
-        const C inv = C(1) / (o.rho[0] + o.rho[1]);
-        C* r = rec + s * REC;
-        for (int a = 0; a < 3; ++a) {
-          const C gsc = -o.rho[0] * (K.G[0][0] * NA[a] + K.G[0][1] * NB[a]) -
-                        o.rho[1] * (K.G[1][0] * NA[a] + K.G[1][1] * NB[a]);
-          r[a] = NA[a];
-          r[3 + a] = NB[a];
-          r[6 + a] = (o.j[a] + C(0.5) * gsc) * inv;
-        }
-        r[9] = o.rho[0];
-        r[10] = o.rho[1];
-      }
-      if (!moments_ok(o)) flag_unstable(status, bad, 1u, K.step);
-      acc[0] += o.rho[0];
-      acc[1] += o.rho[1];
-      acc[2] += o.j[0];
-      acc[3] += o.j[1];
-      acc[4] += o.j[2];
+    for (int a = 0; a < 3; ++a) o.j[a] = jt[a];
+    rho[s] = o.rho[0];
+    rho[N + s] = o.rho[1];
+    if (mask && ((mask[s >> 5] >> (s & 31)) & 1u)) {
+      C* r = rec + s * REC;
+      r[6] = o.j[0];
+      r[7] = o.j[1];
+      r[8] = o.j[2];
+      r[9] = o.rho[0];
+      r[10] = o.rho[1];
     }
-    if (z + 2 <= z1) load_border(z + 2, (k + 3) & 3);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) jc[a] = jn[a];
+    if (!moments_ok(o)) flag_unstable(status, bad, 1u, K.step);
+    acc[0] += o.rho[0];
+    acc[1] += o.rho[1];
+    acc[2] += o.j[0];
+    acc[3] += o.j[1];
+    acc[4] += o.j[2];
   }
-  block_sum5<TY>(acc, red + 5 * int64_t(T.bid));
+  block_sum5<DENS_BLOCK / 64>(acc, red + 5 * int64_t(blockIdx.x));
 }
 
 // Pass C: collision and streaming of every site, the particle force applied
 // where a particle touches; the density ring is filled from the density
-// field written by pass P (two values per site instead of 38).
+// field written by the density pass (two values per site instead of 38).
 template <class S, int TY, int FORCING, bool NOISE, bool MRT>
 __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_, S* __restrict__ dst_,
                                                       const arith_t<S>* __restrict__ rho, FluidConsts<arith_t<S>> K,
@@ -1061,9 +1016,10 @@ static hipError_t pass_a_t(lbmd_ctx* h) {
     }
     if (hipError_t e = prof_end(h)) return e;
   } else {
-    LBMD_BY_TY(L.ty, hipLaunchKernelGGL((k_moments<S, TYV, FORCING>), dim3(L.nblk), dim3(64 * TYV), 0, h->stream, src,
-                                        (C*)h->rho, K, L.tz, L.tiles_x, h->xcd, mask, (C*)h->rec, h->red_fluid, h->status,
-                                        h->bad_step));
+    const int64_t nb = std::min<int64_t>((h->N + DENS_BLOCK - 1) / DENS_BLOCK, DENS_GRID);
+    h->red_fluid_used = nb;
+    hipLaunchKernelGGL(k_dens<S>, dim3(nb), dim3(DENS_BLOCK), 0, h->stream, src, (C*)h->rho, K, mask, (C*)h->rec,
+                       h->red_fluid, h->status, h->bad_step);
   }
   return hipGetLastError();
 }

@@ -212,6 +212,7 @@ struct PartArgs {
   int nx, ny, nz;
   int64_t N;
   double gamma, kT;
+  double G[2][2];        // Shan-Chen coupling matrix (node records formed in the coupling kernel)
   uint64_t seed;
   int64_t step;          // set from *stepp by the kernels that need it
   const int64_t* stepp;  // device step counter

@@ -394,13 +394,20 @@ __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict_
 // one thread per particle for the scattered record loads and the atomics.
 // Same arithmetic as couple_one, with the 8-term sums in tree order.
 constexpr int COUPLE8_BLOCK = 256;
+//
+// rho (may be null): the density field [2][N].  With it the node records
+// hold only the raw momentum (slots 6-8) and the densities (9, 10), as the
+// flat density pass writes them, and each lane forms its node's neighbour
+// sums N_zeta from the field and u_c = (j + g_SC/2)/rho itself; without it
+// the records are complete (fused organisation).
 template <class C>
 __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const double* __restrict__ x,
                                                            const double* __restrict__ v, double* __restrict__ F,
                                                            double* __restrict__ Fc, const int32_t* __restrict__ type,
-                                                           const C* __restrict__ rec, C* __restrict__ gP,
-                                                           C* __restrict__ gS, const int32_t* __restrict__ perm,
-                                                           uint32_t* status, long long* bad) {
+                                                           const C* __restrict__ rec, const C* __restrict__ rho,
+                                                           C* __restrict__ gP, C* __restrict__ gS,
+                                                           const int32_t* __restrict__ perm, uint32_t* status,
+                                                           long long* bad) {
   const int64_t tid = int64_t(blockIdx.x) * (COUPLE8_BLOCK / 8) + (threadIdx.x >> 3);
   const int k = threadIdx.x & 7;
   // every lane of a group takes part in the shuffles; a group past the last
@@ -415,16 +422,50 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
   const double d[3] = {xp[0] - fl[0], xp[1] - fl[1], xp[2] - fl[2]};
   const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
   const double Wk = (ox ? d[0] : 1.0 - d[0]) * (oy ? d[1] : 1.0 - d[1]) * (oz ? d[2] : 1.0 - d[2]);
-  const int64_t nk = (int64_t(wrapi(cell_coord(fl[2], A.nz) + oz, A.nz)) * A.ny +
-                      wrapi(cell_coord(fl[1], A.ny) + oy, A.ny)) * A.nx +
-                     wrapi(cell_coord(fl[0], A.nx) + ox, A.nx);
+  const int X = wrapi(cell_coord(fl[0], A.nx) + ox, A.nx), Y = wrapi(cell_coord(fl[1], A.ny) + oy, A.ny),
+            Z = wrapi(cell_coord(fl[2], A.nz) + oz, A.nz);
+  const int64_t nk = (int64_t(Z) * A.ny + Y) * A.nx + X;
   const C* r = rec + nk * 16;
+  // the node's neighbour sums and coupling velocity
+  C NA[3], NB[3], uc[3];
+  if (rho) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) NA[a] = NB[a] = C(0);
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
+      const int64_t sn = (int64_t(wrapi(Z + cz, A.nz)) * A.ny + wrapi(Y + cy, A.ny)) * A.nx + wrapi(X + cx, A.nx);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const C wr = weight<C>(i) * rho[c * A.N + sn];
+        C(&Nc)[3] = c == 0 ? NA : NB;
+        if (cx) Nc[0] += cx > 0 ? wr : -wr;
+        if (cy) Nc[1] += cy > 0 ? wr : -wr;
+        if (cz) Nc[2] += cz > 0 ? wr : -wr;
+      }
+    }
+    const C ra = r[9], rb = r[10];
+    const C inv = C(1) / (ra + rb);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const C gsc = -ra * (C(A.G[0][0]) * NA[a] + C(A.G[0][1]) * NB[a]) -
+                    rb * (C(A.G[1][0]) * NA[a] + C(A.G[1][1]) * NB[a]);
+      uc[a] = (r[6 + a] + C(0.5) * gsc) * inv;
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      NA[a] = r[a];
+      NB[a] = r[3 + a];
+      uc[a] = r[6 + a];
+    }
+  }
   double gA[3], gB[3], up[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    gA[a] = group8_sum(Wk * 3.0 * double(r[a]));
-    gB[a] = group8_sum(Wk * 3.0 * double(r[3 + a]));
-    up[a] = group8_sum(Wk * double(r[6 + a]));
+    gA[a] = group8_sum(Wk * 3.0 * double(NA[a]));
+    gB[a] = group8_sum(Wk * 3.0 * double(NB[a]));
+    up[a] = group8_sum(Wk * double(uc[a]));
   }
   double R[4] = {0, 0, 0, 0};
   if (A.kT > 0.0) {
@@ -515,6 +556,8 @@ static PartArgs args(const lbmd_ctx* h) {
   A.N = h->N;
   A.gamma = h->p.gamma;
   A.kT = h->p.kT;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) A.G[a][b] = h->p.G[a][b];
   A.seed = h->p.seed;
   A.step = 0;
   A.stepp = h->step_dev;
@@ -578,14 +621,16 @@ hipError_t particles_forces(lbmd_ctx* h) {
   PartArgs A = args(h);
   // pair forces: added by the second half kick
   const int64_t nb = (h->np + COUPLE8_BLOCK / 8 - 1) / (COUPLE8_BLOCK / 8);
+  // two-pass organisation: records hold j and rho only, the density field is current
+  const void* field = organisation_of(h) == LBMD_KERNEL_TWOPASS ? h->rho : nullptr;
   if (h->p.precision == LBMD_FP64)
     hipLaunchKernelGGL(k_couple8<double>, dim3(nb), dim3(COUPLE8_BLOCK), 0, h->stream, A, h->x, h->v, h->F, h->Fc,
-                       h->type, (const double*)h->rec, (double*)h->gP, (double*)h->gS, h->cell_perm, h->status,
-                       h->bad_step);
+                       h->type, (const double*)h->rec, (const double*)field, (double*)h->gP, (double*)h->gS,
+                       h->cell_perm, h->status, h->bad_step);
   else
     hipLaunchKernelGGL(k_couple8<float>, dim3(nb), dim3(COUPLE8_BLOCK), 0, h->stream, A, h->x, h->v, h->F, h->Fc,
-                       h->type, (const float*)h->rec, (float*)h->gP, (float*)h->gS, h->cell_perm, h->status,
-                       h->bad_step);
+                       h->type, (const float*)h->rec, (const float*)field, (float*)h->gP, (float*)h->gS,
+                       h->cell_perm, h->status, h->bad_step);
   return hipGetLastError();
 }
 
