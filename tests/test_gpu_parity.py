@@ -209,9 +209,15 @@ def test_fluid_solvation_force(precision, tol, kernel):
     compare(c, g, o, tol * 5, tol * 5, "lambda")
 
 
-def test_invariant_with_fluid_solvation_on_gpu():
-    c = Case((24, 20, 16), FP64, PAPER, FUSED, G=1.4, gamma=0.8, npart=50, vel_amp=0.05,
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+def test_invariant_with_fluid_solvation_on_gpu(kernel):
+    """Fluid raw momentum + sum (m v + F_c/2) stays constant on the GPU with
+    friction, kappa and lambda solvation (FP64; both organisations: the fused
+    records, and the density pass's sums with the coupling kernel's neighbour
+    sums)."""
+    c = Case((24, 20, 16), FP64, PAPER, kernel, G=1.4, gamma=0.8, npart=50, vel_amp=0.05,
              kappa=((0.3, -0.1),), mass=(400.0,), lambda_fs=((0.05, -0.04),))
+    print("invariant kernel=%d" % kernel, flush=True)
     g = c.gpu_sim()
     first = None
     for k in range(40):
