@@ -384,7 +384,6 @@ __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict_
     for (int a = 0; a < 3; ++a) atomicAdd(&gP[node[k] * 4 + a], C(-W[k] * fc[a]));
 }
 
-
 // Coupling with 8 lanes per particle (single-job path): lane k owns node k
 // of the particle's cell, gathers that node's record, and the 8 partial
 // sums are combined with a butterfly of shuffles inside the lane group
@@ -393,13 +392,13 @@ __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict_
 // and each lane spreads onto its own node.  Eight times the parallelism of
 // one thread per particle for the scattered record loads and the atomics.
 // Same arithmetic as couple_one, with the 8-term sums in tree order.
-constexpr int COUPLE8_BLOCK = 256;
 //
 // rho (may be null): the density field [2][N].  With it the node records
 // hold only the raw momentum (slots 6-8) and the densities (9, 10), as the
-// flat density pass writes them, and each lane forms its node's neighbour
-// sums N_zeta from the field and u_c = (j + g_SC/2)/rho itself; without it
-// the records are complete (fused organisation).
+// streaming density pass writes them, and each lane forms its node's
+// neighbour sums N_zeta from the field and u_c = (j + g_SC/2)/rho itself;
+// without it the records are complete (fused organisation).
+constexpr int COUPLE8_BLOCK = 256;
 template <class C>
 __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const double* __restrict__ x,
                                                            const double* __restrict__ v, double* __restrict__ F,
