@@ -278,8 +278,8 @@ def main():
         accuracy_study(args.workload, args.accuracy)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the path shards by z-slabs across GPUs, "
-              "which is not built); use --gpus 1", file=sys.stderr)
+        print("bench.py: lbmd runs on one GPU only (the step would shard by z-slabs across GPUs, "
+              "which is not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     jobs = None
