@@ -9,12 +9,15 @@
 //             of the pair-force cell list
 //   k_scan_*  exclusive scan of the cell counts, then a scatter into
 //             cell-sorted order
-//   k_forces  trilinear interpolation of u_c and grad rho_zeta from the node
-//             records, friction + solvation (Eq. solvation_kappa) + random
-//             force, conservative pair forces from the cell list and FENE
-//             bonds; the opposite coupling force is spread onto the 8 nodes
-//             with hardware float atomics
-//   k_end     second half kick
+//   k_pairs   conservative pair forces from the cell list and FENE bonds
+//             (second stream, beside the fluid passes; 8 lanes per particle)
+//   k_couple8 trilinear interpolation of u_c and grad rho_zeta from the node
+//             records (forming the neighbour sums from the density field in
+//             the two-pass organisation), friction + solvation (Eq.
+//             solvation_kappa) + random force; the opposite coupling force
+//             is spread onto the 8 nodes with hardware float atomics (8 lanes
+//             per particle, one per node)
+//   k_end     second half kick with the coupling and conservative forces
 // All particle quantities are float64.
 #include <hip/hip_runtime.h>
 
