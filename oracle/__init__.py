@@ -6,9 +6,13 @@ and wrapped here with ctypes.  Only the tests, the package smoke check and the
 benchmark's CPU-baseline leg may import this module; the GPU library never
 does, and this module never imports the GPU library.
 
-Functions with no independent pin are marked "parity unpinned" in their
-docstring; every other function is checked by ``tests/test_oracle_*.py``
-against closed forms, invariants, published test vectors or brute force.
+Every function here is checked by ``tests/test_oracle_*.py`` against
+something other than itself: closed forms, invariants, values the paper
+prints (the Debye-Hueckel energy at its cut-off, the definition of the
+Bjerrum length), the relaxation factor of each mode group, equipartition,
+published test vectors or brute force.  None is currently unpinned; a
+function added without such a check must say "parity unpinned" in its
+docstring.
 """
 import ctypes
 import os

@@ -543,3 +543,107 @@ def test_sampled_pieces_match_full_step():
     for i in range(19):
         dst = (((z + c[i, 2]) % 4) * 5 + (y + c[i, 1]) % 5) * 6 + (x + c[i, 0]) % 6
         assert np.abs(s.f[:, i, dst] - out[:, i]).max() < 1e-15
+
+
+def _mode_subspaces():
+    """w-orthogonal decomposition of population space, built here from the
+    velocity polynomials and the weights, independently of the oracle's own
+    mode basis (Appendix: the modes are the moments of f; the hydrodynamic
+    ones are mass, momentum and the stress).  Returns unnormalised vectors
+    g (so that a perturbation is delta f_i = w_i g_i) per group:
+      bulk   c^2 - 1 (trace of the stress, w-orthogonal to 1);
+      shear  the traceless stress c_a c_b - delta_ab c^2 / 3 (5 independent);
+      ghost  the 9-dimensional w-orthogonal complement of {1, c_a, c_a c_b}
+             (the kinetic modes, which carry no hydrodynamic moment)."""
+    c, w = oracle.lattice()
+    c = c.astype(float)
+    c2 = (c ** 2).sum(axis=1)
+    hydro = [np.ones(19)] + [c[:, a] for a in range(3)] + \
+            [c[:, a] * c[:, b] for a in range(3) for b in range(a, 3)]
+    H = np.stack(hydro, axis=1)  # 19 x 10
+    W = np.diag(w)
+    proj = H @ np.linalg.solve(H.T @ W @ H, H.T @ W)  # w-orthogonal projector on span(H)
+    rng = np.random.default_rng(11)
+    ghost = [(np.eye(19) - proj) @ rng.normal(size=19) for _ in range(9)]
+    shear = [c[:, 0] * c[:, 1], c[:, 1] * c[:, 2], c[:, 0] * c[:, 2],
+             c[:, 0] ** 2 - c[:, 1] ** 2, c[:, 0] ** 2 + c[:, 1] ** 2 - 2 * c[:, 2] ** 2]
+    return c, w, {"bulk": [c2 - 1.0], "shear": shear, "ghost": ghost}
+
+
+@pytest.mark.parametrize("lams", [(-1.9, -0.3, -1.0, -1.5), (-0.4, -1.7, -1.2, -0.8)])
+def test_mrt_relaxes_each_mode_group_with_its_eigenvalue(lams):
+    """Appendix, Eqs. collis and MODES: a mode relaxes as
+    m* = m_eq + (1 + lambda_k)(m - m_eq).  At rest (u = 0, no force) a
+    perturbation lying in one non-hydrodynamic group leaves mass and momentum,
+    hence the equilibrium w_i rho, unchanged, so the collision must multiply it
+    by exactly (1 + lambda) of that group: lambda_b for the bulk mode,
+    lambda_s for the shear modes and lambda_ghost for the nine kinetic modes."""
+    lam_b, lam_s, lam_m, lam_g = lams
+    want = {"bulk": lam_b, "shear": lam_s, "ghost": lam_g}
+    shape = (3, 3, 3)
+    N = 27
+    P = oracle.make_params(shape, G=((0, 0), (0, 0)), mrt=lams)
+    c, w, groups = _mode_subspaces()
+    site = 13
+    for name, vecs in groups.items():
+        for k, g in enumerate(vecs):
+            f = oracle.init_populations(P, uniform_rho(shape, 1.3, 0.7))
+            rho = f[:, :, site].sum(axis=1)
+            eps = (1e-3, -2e-3)
+            for z in range(2):
+                f[z, :, site] += eps[z] * w * g
+            out = oracle.site_collide(P, 0, f, site)
+            for z in range(2):
+                rest = w * rho[z]
+                assert np.abs(out[z] - rest - (1 + want[name]) * eps[z] * w * g).max() < 1e-15, (name, k)
+    # momentum modes: relaxed towards rho_z u, their eigenvalue enters only
+    # through the component momenta; a pure interdiffusion current (j_A = -j_B)
+    # decays by (1 + lambda_M) at G = 0
+    f = oracle.init_populations(P, uniform_rho(shape, 1.0, 1.0))
+    f[0, :, site] += 1e-3 * w * c[:, 0] * 3.0
+    f[1, :, site] -= 1e-3 * w * c[:, 0] * 3.0
+    out = oracle.site_collide(P, 0, f, site)
+    jA_in = f[0, :, site] @ c[:, 0]
+    jA_out = out[0] @ c[:, 0]
+    assert abs(jA_out - (1 + lam_m) * jA_in) < 1e-16
+
+
+def test_mrt_equipartition_per_mode_group():
+    """Fluctuation-dissipation with four distinct eigenvalues (Appendix, Eq.
+    MODES: the noise of each mode must compensate its own relaxation).  In a
+    resting two-component fluid at G = 0 the stationary population covariance
+    is mu_zeta w_i delta_ij with mu_zeta = rho_zeta kT / c_s^2, so every mode
+    sum_i g_i f_zeta,i has variance mu_zeta sum_i w_i g_i^2 whatever its
+    eigenvalue, and each component's momentum has variance rho_zeta kT per
+    axis.  A noise amplitude taken from another group's eigenvalue breaks this
+    for that group."""
+    lams = (-1.9, -0.3, -1.0, -1.5)  # bulk, shear, momentum, ghost
+    shape = (8, 8, 8)
+    kT = 1e-4
+    rA, rB = 1.2, 0.8
+    P = oracle.make_params(shape, G=((0, 0), (0, 0)), kT=kT, seed=23, mrt=lams)
+    s = oracle.Sim(P, uniform_rho(shape, rA, rB))
+    c, w, groups = _mode_subspaces()
+    s.step(120)
+    acc = {name: [0.0, 0.0] for name in groups}
+    jacc = [0.0, 0.0]
+    nsamp = 0
+    for _ in range(100):
+        s.step(2)
+        nsamp += 1
+        for z, r in enumerate((rA, rB)):
+            fz = s.f[z]  # [19][N]
+            mu = r * kT / CS2
+            for name, vecs in groups.items():
+                v = 0.0
+                for g in vecs:
+                    m = g @ fz - r * (w @ g)  # fluctuation of the mode (its rest value is r sum w g)
+                    v += np.mean(m ** 2) / (mu * (w @ (g * g)))
+                acc[name][z] += v / len(vecs)
+            j = fz.T @ c  # [N][3]
+            jacc[z] += np.mean(j ** 2) / (r * kT)
+    for name in groups:
+        for z in range(2):
+            assert abs(acc[name][z] / nsamp - 1.0) < 0.05, (name, z, acc[name][z] / nsamp)
+    for z in range(2):
+        assert abs(jacc[z] / nsamp - 1.0) < 0.05, (z, jacc[z] / nsamp)

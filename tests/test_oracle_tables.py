@@ -216,3 +216,39 @@ def test_conservative_forces_antisymmetric():
     for p in (0, 7, 39):
         st1, Fp = oracle.conservative_force_one(P, x, p, t, bonds)
         assert np.array_equal(Fp, F[p])
+
+
+@pytest.mark.parametrize("lB", [0.6, 1.0, 2.3])
+def test_debye_hueckel_bjerrum_length_and_cutoff_energy(lB):
+    """Screened electrostatics in the paper's reduced units.
+
+    * Sec. 3 (remapping to physical units): the Bjerrum length l_B is the
+      distance at which two unit charges interact with an energy of kT (= 1
+      here), so the unscreened pair energy of q_i = q_j = 1 at r = l_B is 1.
+    * Sec. 4 (polyelectrolytes): with screening length kappa_D^-1 = 4 l_B and
+      cut-off r_c = 6 l_B the screened energy of an ion pair at the cut-off is
+      about 0.04 kT -- for every l_B, since only r / l_B enters.
+    Both fail if the l_B prefactor is dropped or misplaced."""
+    P = oracle.make_params((40, 40, 40), dh=(0.0, 10.0, lB))
+    assert abs(oracle.pair_energy(P, 1, lB, 1.0) - 1.0) < 1e-14
+    assert abs(oracle.pair_energy(P, 1, lB, -1.0) + 1.0) < 1e-14
+    P = oracle.make_params((40, 40, 40), dh=(1.0 / (4.0 * lB), 6.0 * lB, lB))
+    u_cut = oracle.pair_energy(P, 1, 6.0 * lB * (1.0 - 1e-12), 1.0)
+    assert round(u_cut, 2) == 0.04
+    assert oracle.pair_energy(P, 1, 6.0 * lB, 1.0) == 0.0  # zero at and beyond r_c
+
+
+@pytest.mark.parametrize("lB,qq", [(0.6, -2.5), (2.3, 4.0)])
+def test_debye_hueckel_force_with_bjerrum_length_and_charges(lB, qq):
+    """Radial DH force = -dU/dr (central differences of the pinned energy) at
+    l_B != 1 and q_i q_j != 1, and linear in both l_B and q_i q_j."""
+    P = oracle.make_params((40, 40, 40), dh=(0.8, 3.0, lB))
+    P1 = oracle.make_params((40, 40, 40), dh=(0.8, 3.0, 1.0))
+    for r in np.linspace(0.4, 2.95, 25):
+        h = 1e-6
+        num = -(oracle.pair_energy(P, 1, r + h, qq) - oracle.pair_energy(P, 1, r - h, qq)) / (2 * h)
+        ana = oracle.pair_force(P, 1, r, qq)
+        assert abs(num - ana) <= 1e-6 * max(1.0, abs(ana))
+        assert abs(ana - lB * qq * oracle.pair_force(P1, 1, r, 1.0)) <= 1e-13 * abs(ana)
+    # like charges repel: positive radial force
+    assert oracle.pair_force(P, 1, 1.0, abs(qq)) > 0.0
