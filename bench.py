@@ -12,8 +12,10 @@ value            lattice updates per second (MLUPS) over the timed K steps
 roofline         the fused collide-stream kernel: algorithmic bytes per launch
                  (38 populations read + 38 written per site) over its average
                  launch duration, from HIP events on the stream it runs on
-cpu_baseline     the FP64 oracle on the host cores, on a 64^3 box of the same
-                 workload (same densities recipe, same particle number density)
+cpu_baseline     the FP64 oracle on the host cores (one thread and all usable
+                 cores), on a 64^3 box of the same workload (same densities
+                 recipe, same particle number density), and the full 32^3 FP64
+                 workload of 100 steps
 """
 import argparse
 import hashlib
@@ -86,20 +88,43 @@ def setup(workload, stream, kernel, tiling, precision=None):
     return sim, w, len(x)
 
 
-def cpu_baseline(workload, target_s=15.0):
-    """The FP64 oracle as it stands, single thread, on a 64^3 box of the
-    same workload: MLUPS over as many steps as fit in about target_s."""
+def host_cpu():
+    """Model name and logical CPU counts of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def _oracle_sim(w, shape, forcing=None):
     import oracle
     from paper_1306_0788_amd import workloads
-    w = workloads.WORKLOADS[workload]
-    shape = (64, 64, 64)
     rho = workloads.initial_densities(shape, w["seed"]).reshape(2, -1)
     x, bonds = workloads.particles_for(w, shape)
+    forcing = forcing or w["forcing"]
     P = oracle.make_params(shape, tau=w["tau"], G=w["G"],
-                           forcing=oracle.FORCE_SHIFT if w["forcing"] == "shift" else oracle.FORCE_PAPER,
+                           forcing=oracle.FORCE_SHIFT if forcing == "shift" else oracle.FORCE_PAPER,
                            gamma=w["gamma"], kT=w["kT"], seed=w["seed"], kappa=w["kappa"], mass=w["mass"],
                            charge=w["charge"], wca=w["wca"], fene=w["fene"], dh=w["dh"])
-    s = oracle.Sim(P, rho, x, None, None, bonds)
+    return oracle.Sim(P, rho, x, None, None, bonds), len(x)
+
+
+def _oracle_mlups(w, shape, threads, target_s):
+    """MLUPS of the oracle on `shape` with `threads` OpenMP threads over as
+    many steps as fit in about target_s (at least 2)."""
+    import oracle
+    oracle.set_threads(threads)
+    s, npart = _oracle_sim(w, shape)
     t0 = time.perf_counter()
     s.step(1)
     t1 = time.perf_counter()
@@ -107,10 +132,45 @@ def cpu_baseline(workload, target_s=15.0):
     s.step(n)
     t2 = time.perf_counter()
     steps = n + 1
-    mlups = 64 ** 3 * steps / (t2 - t0) / 1e6
-    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "FP64 oracle, 1 thread, %d steps of a 64^3 box of workload %s (%d particles)"
-                      % (steps, workload, len(x))}
+    return int(np.prod(shape)) * steps / (t2 - t0) / 1e6, steps, npart
+
+
+def cpu_baseline(workload, target_s=10.0):
+    """The FP64 oracle as it stands, timed on this host's cores: on a 64^3 box
+    of the benchmarked workload (same density recipe, same particle number
+    density) with one thread and with every usable core (its OpenMP loops
+    give bit-identical results for any thread count), and the full 32^3
+    FP64 workload (64 particles, 100 steps) on every core.  value = the
+    all-core MLUPS of the 64^3 sample."""
+    import oracle
+    from paper_1306_0788_amd import workloads
+    w = workloads.WORKLOADS[workload]
+    model, ncpu, usable = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or usable
+    shape = (64, 64, 64)
+    one, steps1, npart = _oracle_mlups(w, shape, 1, target_s)
+    print("bench: CPU oracle 1 thread %.3f MLUPS" % one, file=sys.stderr, flush=True)
+    allc, stepsN, _ = _oracle_mlups(w, shape, threads, target_s)
+    print("bench: CPU oracle %d threads %.3f MLUPS" % (threads, allc), file=sys.stderr, flush=True)
+    # the 32^3 FP64 workload in full; its velocity-shift forcing reaches zero
+    # density at step 35 from this start, so the 100 steps run with the
+    # paper's forcing (as the parity tests' 100-step runs do)
+    oracle.set_threads(threads)
+    c1 = workloads.WORKLOADS["c1"]
+    s, n1 = _oracle_sim(c1, c1["shape"], forcing="paper")
+    t0 = time.perf_counter()
+    st = s.step(c1["steps"])
+    t_c1 = time.perf_counter() - t0
+    oracle.set_threads(1)
+    return {"value": round(allc, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle, %d OpenMP threads, %d steps of a 64^3 box of workload %s (%d particles)"
+                      % (threads, stepsN, workload, npart),
+            "single_thread_MLUPS": round(one, 4), "single_thread_steps": steps1,
+            "host": {"cpu_model": model, "nproc": ncpu, "usable_cpus": usable},
+            "c1_full": {"lattice": list(c1["shape"]), "particles": n1, "steps": c1["steps"],
+                        "forcing": "paper", "threads": threads, "seconds": round(t_c1, 3),
+                        "MLUPS": round(int(np.prod(c1["shape"])) * c1["steps"] / t_c1 / 1e6, 4),
+                        "status": "ok" if st == oracle.OK else "unstable"}}
 
 
 def copy_calibration():

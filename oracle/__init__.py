@@ -32,11 +32,11 @@ MAXTYPES = 8
 
 
 def build(force=True):
-    """Compile orc.c into liboracle.so with gcc (strict IEEE, no fast-math)."""
+    """Compile orc.c into liboracle.so with gcc (strict IEEE, no fast-math, OpenMP)."""
     src = os.path.join(_HERE, "orc.c")
     if force or not os.path.exists(_LIBPATH) or os.path.getmtime(_LIBPATH) < os.path.getmtime(src):
         tmp = _LIBPATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
                                "-ffp-contract=off", src, "-o", tmp, "-lm"])
         os.replace(tmp, _LIBPATH)
     return _LIBPATH
@@ -112,6 +112,8 @@ def lib():
             build()
         L = ctypes.CDLL(_LIBPATH)
         L.orc_lattice.argtypes = [_I32, _D]
+        L.orc_set_threads.argtypes = [ctypes.c_int32]
+        L.orc_get_threads.restype = ctypes.c_int32
         L.orc_mode_basis.argtypes = [_D, _D]
         L.orc_equilibrium.argtypes = [ctypes.c_double, _D, _D]
         L.orc_forcing_term.argtypes = [ctypes.c_double] * 3 + [_D, _D, _D]
@@ -153,6 +155,16 @@ def _dp(a):
 def _c64(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's site and particle loops (bit-identical
+    results for any count)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
 
 
 def lattice():

@@ -28,8 +28,18 @@
  */
 #include "orc.h"
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads: the per-site loops (moments, neighbour sums, the collision and
+   streaming of every site) and the per-particle force loops are split over
+   OpenMP threads; every site and particle is still computed by the same
+   serial arithmetic, and the global sums and the spread onto the nodes stay
+   serial in a fixed order, so any thread count gives bit-identical
+   results. */
+void orc_set_threads(int32_t n) { omp_set_num_threads(n > 0 ? n : 1); }
+int32_t orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* D3Q19 velocities (Appendix, Eq. velo), opposite pairs adjacent.  The
    order inside the groups is not fixed by the paper; this one is used by
@@ -212,6 +222,7 @@ void orc_init_populations(const orc_params* P, const double* rho, double* f) {
 /* S1: rho_zeta = sum_i f_zeta i, raw momentum sum_zeta sum_i f c_i. */
 void orc_moments(const orc_params* P, const double* f, double* rho, double* j, double* jc) {
   int64_t N = nsites(P);
+#pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; s++) {
     double jt[3] = {0, 0, 0};
     for (int c = 0; c < 2; c++) {
@@ -236,6 +247,7 @@ void orc_moments(const orc_params* P, const double* f, double* rho, double* j, d
    vector r'-r is taken as w_i c_i with proportionality constant 1. */
 void orc_neighbour_sums(const orc_params* P, const double* rho, double* Ns) {
   int64_t N = nsites(P);
+#pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; s++) {
     int x, y, z;
     coords_of(P, s, &x, &y, &z);
@@ -393,6 +405,7 @@ int orc_conservative_force_one(const orc_params* P, int64_t np, const double* x,
 int orc_conservative_forces(const orc_params* P, int64_t np, const double* x, const int32_t* type,
                             int64_t nbonds, const int32_t* bonds, double* F) {
   int st = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 64) reduction(min : st)
   for (int64_t p = 0; p < np; p++)
     if (orc_conservative_force_one(P, np, x, type, nbonds, bonds, p, &F[3 * p]) != ORC_OK)
       st = ORC_EUNSTABLE;
@@ -423,14 +436,20 @@ static int check_params(const orc_params* P) {
    fin  [2][19] post-streaming populations at the site
    gsc  [2][3]  Shan-Chen force per component, gP [3] particle force (total)
    out  [2][19] post-collision populations */
+static double E[ORC_Q][ORC_Q], B[ORC_Q];
+static void basis_init(void) {
+#pragma omp critical(orc_basis)
+  {
+    static int ready = 0;
+    if (!ready) {
+      orc_mode_basis(&E[0][0], B);
+      ready = 1;
+    }
+  }
+}
+
 static void collide_site(const orc_params* P, int64_t step, int64_t site, const double* fin,
                          const double* gsc, const double* gP, const double* gfs, double* out) {
-  static int basis_ready = 0;
-  static double E[ORC_Q][ORC_Q], B[ORC_Q];
-  if (!basis_ready) {
-    orc_mode_basis(&E[0][0], B);
-    basis_ready = 1;
-  }
   double rho[2], jc[2][3];
   for (int c = 0; c < 2; c++) {
     rho[c] = 0.0;
@@ -606,6 +625,7 @@ int orc_site_collide(const orc_params* P, int64_t step, const double* f, int64_t
   }
   for (int c = 0; c < 2; c++)
     for (int a = 0; a < 3; a++) gsc[3 * c + a] = -rho[c] * (P->G[c][0] * Ns[0][a] + P->G[c][1] * Ns[1][a]);
+  basis_init();
   collide_site(P, step, site, fin, gsc, gP, NULL, out);
   return ORC_OK;
 }
@@ -648,11 +668,13 @@ int orc_step(const orc_params* P, int64_t step, double* f, int64_t np, double* x
   orc_neighbour_sums(P, rho, Ns);
   for (int c = 0; c < 2; c++)
     for (int a = 0; a < 3; a++)
+#pragma omp parallel for schedule(static)
       for (int64_t s = 0; s < N; s++)
         gsc[((int64_t)c * 3 + a) * N + s] =
             -rho[c * N + s] * (P->G[c][0] * Ns[(0 * 3 + a) * N + s] + P->G[c][1] * Ns[(1 * 3 + a) * N + s]);
   /* S3 */
   for (int a = 0; a < 3; a++)
+#pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N; s++)
       uc[a * N + s] = (j[a * N + s] + 0.5 * (gsc[(0 * 3 + a) * N + s] + gsc[(1 * 3 + a) * N + s])) /
                       (rho[s] + rho[N + s]);
@@ -666,6 +688,7 @@ int orc_step(const orc_params* P, int64_t step, double* f, int64_t np, double* x
     }
   }
   /* S5 */
+#pragma omp parallel for schedule(static)
   for (int64_t p = 0; p < np; p++) {
     int t = type ? type[p] : 0;
     int64_t node[8];
@@ -702,7 +725,10 @@ int orc_step(const orc_params* P, int64_t step, double* f, int64_t np, double* x
     if (orc_conservative_forces(P, np, x, type, nbonds, bonds, F) != ORC_OK) status = ORC_EUNSTABLE;
     for (int64_t p = 0; p < 3 * np; p++) F[p] += Fc[p];
   }
-  /* S7 + S8 */
+  /* S7 + S8 (streaming is a permutation: every site writes its own
+     targets) */
+  basis_init();
+#pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; s++) {
     double fin[2 * ORC_Q], out[2 * ORC_Q], gs[6], gp[3], gf[6];
     for (int c = 0; c < 2; c++)

@@ -65,6 +65,11 @@ void orc_interp_weights(const double* x, int32_t nx, int32_t ny, int32_t nz,
 double orc_pair_energy(const orc_params* P, int32_t kind, double r, double qq);
 double orc_pair_force(const orc_params* P, int32_t kind, double r, double qq);
 
+/* OpenMP threads of the per-site and per-particle loops (results do not
+   depend on the count). */
+void orc_set_threads(int32_t n);
+int32_t orc_get_threads(void);
+
 /* ---- whole-lattice pieces ---- */
 /* moments: rho [2][N], j (raw, both components summed) [3][N],
    jc (raw per component) [2][3][N] (may be NULL) */

@@ -647,3 +647,26 @@ def test_mrt_equipartition_per_mode_group():
             assert abs(acc[name][z] / nsamp - 1.0) < 0.05, (name, z, acc[name][z] / nsamp)
     for z in range(2):
         assert abs(jacc[z] / nsamp - 1.0) < 0.05, (z, jacc[z] / nsamp)
+
+
+def test_thread_count_gives_bit_identical_steps():
+    """The oracle's OpenMP loops split independent sites and particles only;
+    sums and the spread stay serial, so 1 and 4 threads agree bit for bit
+    (fluid, particles, conservation sums) with noise, pair forces and bonds."""
+    shape = (9, 7, 6)
+    N = int(np.prod(shape))
+    g = np.random.default_rng(5)
+    rho = 1.0 + 0.01 * (2 * g.random((2, N)) - 1)
+    x = np.array([[1.2, 1.3, 1.1], [2.17, 1.3, 1.1], [5.5, 4.2, 3.3], [7.9, 6.1, 0.4]])
+    bonds = np.array([[0, 1]], np.int32)
+    res = []
+    for nt in (1, 4):
+        oracle.set_threads(nt)
+        P = oracle.make_params(shape, G=((0, 1.3), (1.3, 0)), gamma=0.7, kT=1e-4, seed=9, kappa=((0.1, -0.05),),
+                               mass=(2000.0,), charge=(1.0,), wca=(1.0, 1.0), fene=(30.0, 1.5), dh=(1.0, 2.5, 1.0))
+        s = oracle.Sim(P, rho, x, bonds=bonds)
+        assert s.step(6) == oracle.OK
+        res.append((s.f.copy(), s.x.copy(), s.v.copy(), s.F.copy(), s.red.copy()))
+    oracle.set_threads(1)
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
