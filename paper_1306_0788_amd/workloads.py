@@ -20,8 +20,10 @@ dataset):
   * emulsion jobs (serving): cubic box L = round(exp(U[ln 32, ln 128])),
     non-overlapping A droplets (periodic distance > r1 + r2 + 2) with radius
     U[4, 12] until the droplet volume reaches a fraction U[0.1, 0.3];
-    rho_A = 0.1 + 1.8 s, rho_B = 0.1 + 1.8 (1 - s) with the smooth indicator
-    s = (1 - tanh((d - R)/2))/2 of the nearest droplet; G_AB = U[1.6, 2.2];
+    G_AB = U[1.6, 2.2]; rho_A = b + (a - b) s, rho_B = b + (a - b)(1 - s)
+    between the bulk coexistence densities a > b of that G_AB (total
+    density 2; `coexistence`) with the smooth indicator
+    s = (1 - tanh((d - R)/2))/2 of the nearest droplet;
     log-uniform 100..10,000 particles uniform in the box, kappa_A = -0.05
     (drawn to the A droplets), gamma = 1, m = 100; 500 steps; arrivals a
     Poisson stream of 20 jobs/s.
@@ -205,6 +207,22 @@ def particles_for(w, shape=None):
     return chains(nch, spec["nbeads"], shape, w["seed"], spec["bond"], spec["min_dist"])
 
 
+def coexistence(G, total=2.0):
+    """Bulk coexistence densities (a, b), a > b, a + b = total, of a symmetric
+    two-component mixture with coupling G between the components: the
+    non-trivial root of equal chemical potentials of the bulk free energy
+    (Sec. 2, Eq. fbulk), ln(a / b) = G (a - b), by Newton's method.  Used
+    only to lay out initial densities; the time step never calls it."""
+    if G * total <= 2.0:
+        return total / 2, total / 2  # below the spinodal: the mixture is stable
+    a = 0.999 * total
+    for _ in range(200):
+        F = math.log(a / (total - a)) - G * (2.0 * a - total)
+        dF = 1.0 / a + 1.0 / (total - a) - 2.0 * G
+        a = min(max(a - F / dF, total / 2 + 1e-12), total * (1 - 1e-15))
+    return a, total - a
+
+
 def emulsion_job(seed, index):
     """Parameters and inputs of serving job `index` of stream `seed`:
     dict(shape, G, rho [2][N], x [n][3], kappa, gamma, mass, steps)."""
@@ -243,9 +261,11 @@ def emulsion_job(seed, index):
         ind = 0.5 * (1.0 - np.tanh((np.sqrt(dx * dx + dy * dy + dz * dz) - R) / 2.0))
         sub = np.ix_(idx[2], idx[1], idx[0])
         s[sub] = np.maximum(s[sub], ind)
-    rho = np.stack([0.1 + 1.8 * s, 0.1 + 1.8 * (1.0 - s)]).reshape(2, -1)
     n = int(round(math.exp(g.uniform(math.log(100.0), math.log(10000.0)))))
-    return dict(shape=(L, L, L), G=float(g.uniform(1.6, 2.2)), rho=rho, x=g.random((n, 3)) * L,
+    G = float(g.uniform(1.6, 2.2))
+    a, b = coexistence(G)
+    rho = np.stack([b + (a - b) * s, b + (a - b) * (1.0 - s)]).reshape(2, -1)
+    return dict(shape=(L, L, L), G=G, rho=rho, x=g.random((n, 3)) * L,
                 kappa=(-0.05, 0.0), gamma=1.0, mass=100.0, steps=500, droplets=len(radii))
 
 

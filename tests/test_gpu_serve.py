@@ -63,6 +63,44 @@ def test_batch_equals_alone_without_particles(kT):
         assert np.array_equal(s.populations(), ref.populations()), j["shape"]
 
 
+def test_batch_jobs_match_the_oracle():
+    """Three jobs of different sizes with particles, started between the
+    coexistence densities of their own G (the served jobs' recipe), advanced
+    together through lbmd_batch_* and compared element by element with the
+    oracle: FP32 tolerance 1e-5 per step on the populations, and the
+    particles' positions, velocities and forces."""
+    import oracle
+    from parity_cases import min_image_err, rel_err
+
+    def droplet_job(L, G, R, npart, seed):
+        a, b = workloads.coexistence(G)
+        z, y, x = np.meshgrid(np.arange(L[2]), np.arange(L[1]), np.arange(L[0]), indexing="ij")
+        d = np.sqrt((x - L[0] / 2) ** 2 + (y - L[1] / 2) ** 2 + (z - L[2] / 2) ** 2)
+        s_ = 0.5 * (1 - np.tanh((d - R) / 2.0))
+        rho = np.stack([b + (a - b) * s_, b + (a - b) * (1 - s_)]).reshape(2, -1)
+        return dict(shape=L, G=G, rho=rho, x=workloads.free_particles(npart, L, seed), kappa=(-0.05, 0.0),
+                    gamma=1.0, mass=100.0, kT=0.0, seed=seed)
+
+    jobs = [droplet_job((20, 18, 16), 1.7, 4.0, 30, 1), droplet_job((33, 29, 23), 1.9, 6.0, 120, 2),
+            droplet_job((12, 40, 9), 1.6, 3.5, 15, 3)]
+    steps = [9, 14, 6]
+    print("batch jobs vs oracle", flush=True)
+    sims, state, st = run_batch(jobs, steps, chunk=4)
+    for j, n, sim, stt in zip(jobs, steps, sims, state):
+        assert stt == lbmd.DONE and sim.step_index == n
+        P = oracle.make_params(j["shape"], G=((0, j["G"]), (j["G"], 0)), gamma=j["gamma"], kappa=(j["kappa"],),
+                               mass=(j["mass"],))
+        o = oracle.Sim(P, j["rho"], j["x"])
+        assert o.step(n) == oracle.OK
+        e = rel_err(sim.populations(), o.f)
+        print("shape %s, %d steps: populations rel err %.2e" % (j["shape"], n, e), flush=True)
+        assert e <= 1e-5 * n
+        x, v, F, Fc = sim.particles()
+        assert min_image_err(x, o.x, j["shape"]) <= 1e-5 * n
+        assert np.abs(v - o.v).max() <= 1e-5 * n * max(np.abs(o.v).max(), 1e-3)
+        assert np.abs(F - o.F).max() <= 1e-5 * n * max(np.abs(o.F).max(), 1e-6)
+
+
 def test_batch_with_particles_matches_alone():
     jobs = [job((24, 20, 16), 1.4, 6, npart=40), job((48, 32, 20), 1.6, 7, npart=300), job((16, 16, 16), 1.3, 8)]
     steps = [10, 14, 9]

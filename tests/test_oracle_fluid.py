@@ -670,3 +670,32 @@ def test_thread_count_gives_bit_identical_steps():
     oracle.set_threads(1)
     for a, b in zip(*res):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("G,survives", [(1.9, True), (2.0, False)])
+def test_small_droplet_stability_boundary(G, survives):
+    """Failure boundary of the served emulsion jobs, pinned in the oracle at
+    their initialisation: an A droplet of radius 4 (the smallest the jobs
+    draw) in B, tanh profile of width 2 between the bulk coexistence
+    densities of G (Sec. 2, Eq. fbulk), 100 solvated particles
+    (kappa_A = -0.05, gamma = 1, m = 100).  At G = 1.9 it lives through the
+    jobs' 500 steps; at G = 2.0 the minority density inside the droplet
+    reaches zero within 100 steps -- the Shan-Chen failure of Sec. 3, a
+    property of the model (psi = rho) at that coupling and curvature, which
+    the served jobs with G above about 1.9 and small droplets also meet."""
+    from paper_1306_0788_amd import workloads
+    L, R = 16, 4.0
+    a, b = workloads.coexistence(G)
+    x, y, z = sites((L, L, L))
+    d = np.sqrt((x - L / 2) ** 2 + (y - L / 2) ** 2 + (z - L / 2) ** 2)
+    s_ = 0.5 * (1 - np.tanh((d - R) / 2.0))
+    rho = np.stack([b + (a - b) * s_, b + (a - b) * (1 - s_)])
+    xp = workloads.free_particles(100, (L, L, L), 4)
+    P = oracle.make_params((L, L, L), G=((0, G), (G, 0)), gamma=1.0, kappa=((-0.05, 0.0),), mass=(100.0,))
+    sim = oracle.Sim(P, rho, xp)
+    st = sim.step(500)
+    if survives:
+        assert st == oracle.OK and sim.step_index == 500
+        assert sim.rho()[0].max() > 1.8  # still a droplet
+    else:
+        assert st == oracle.EUNSTABLE and sim.step_index < 100
