@@ -219,6 +219,36 @@ int lbmd_get_particles(lbmd_handle h, double* pos, double* vel, double* force, d
    (resume, fault injection).  Errors: LBMD_EINVAL on a NULL pointer. */
 int lbmd_set_populations(lbmd_handle h, const double* pop);
 
+/* Checkpoint and resume.  The dynamic state of a simulation is its
+   post-streaming populations (Appendix: f_i(r, t) is the whole fluid state),
+   its particles' positions, velocities, total and coupling forces (velocity
+   Verlet needs F(n) to take step n) and types, and the step index, from which
+   every random draw of a step follows (the Philox counter holds the step:
+   Appendix, Eq. MODES noise; Sec. 2, Eq. NEWTON random force).  Parameters,
+   particle types, potentials, bonds, MRT, lambda and tiling belong to the
+   handle and are not part of the state.
+
+   lbmd_get_state writes the state into the host buffer buf as an opaque,
+   versioned blob (the populations in their stored form, so a resume is exact
+   in every precision).  With buf == NULL it only sets *bytes to the size
+   needed.  If *bytes is too small it sets *bytes to the size needed and
+   returns LBMD_EINVAL.  On success *bytes receives the size written.  Waits
+   for the stream.  Returns the latched status (the state is written either
+   way).
+
+   lbmd_set_state replaces the handle's state with a blob from lbmd_get_state
+   of a handle with the same lattice size, precision (and rho0 for deviation
+   storage); a different particle count is applied as by lbmd_set_particles
+   (bonds then dropped).  The step index, the device status latch and the
+   sums are reset to the blob's step; captured graphs are dropped.  Taking K
+   steps after a restore gives the same result as taking them on the handle
+   the state came from (bit for bit where the step is deterministic; the
+   spread's float atomics can change the order of additions).  Errors:
+   LBMD_EINVAL (NULL, foreign or truncated blob, size or precision mismatch,
+   bad type), LBMD_ESTATE (in a batch), LBMD_ENOMEM, LBMD_EDEVICE. */
+int lbmd_get_state(lbmd_handle h, void* buf, size_t* bytes);
+int lbmd_set_state(lbmd_handle h, const void* buf, size_t bytes);
+
 /* Conservation sums of the state at the start of the most recent step, in
    float64: out[0..1] = sum rho_A, sum rho_B; out[2..4] = raw fluid momentum
    sum_zeta,i f c_i; out[5..7] = sum_p (m v_p + F_coup,p / 2).  With a

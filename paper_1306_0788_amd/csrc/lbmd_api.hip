@@ -47,6 +47,10 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+// the populations were replaced from outside a step: derived fields kept
+// between steps are stale
+void state_changed(lbmd_ctx* h) { (void)h; }
+
 // drop the captured step sequences (the launch sequence changed)
 void graph_invalidate(lbmd_ctx* h) {
   for (int c = 0; c < 2; ++c)
@@ -370,6 +374,25 @@ int autotune(lbmd_ctx* h, int reps, const char* cache_path, int32_t* chosen, dou
   return LBMD_OK;
 }
 
+}  // namespace
+
+namespace {
+// Checkpoint blob: this header, then the stored populations of the current
+// buffer as raw storage words [2][19][N] (pull layout), then the particles'
+// x, v, F, F_coup ([n][3] float64 each) and types ([n] int32).
+struct StateHeader {
+  char magic[8];
+  int32_t version, precision;
+  int32_t nx, ny, nz, pad;
+  int64_t np, step;
+  double rho0;
+};
+constexpr char kStateMagic[8] = {'L', 'B', 'M', 'D', 'S', 'T', 'A', 'T'};
+constexpr int32_t kStateVersion = 1;
+
+size_t state_bytes(const lbmd_ctx* h, int64_t np) {
+  return sizeof(StateHeader) + size_t(2) * 19 * size_t(h->N) * h->s_bytes + size_t(np) * (4 * 3 * sizeof(double) + sizeof(int32_t));
+}
 }  // namespace
 
 extern "C" {
@@ -771,6 +794,114 @@ int lbmd_set_populations(lbmd_handle h, const double* pop) {
   HIPCHECK(h, hipMemcpyAsync(h->export_tmp, pop, 38 * h->N * sizeof(double), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(h, fluid_import(h, h->export_tmp));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
+  state_changed(h);
+  return LBMD_OK;
+}
+
+
+int lbmd_get_state(lbmd_handle h, void* buf, size_t* bytes) {
+  if (!h || !bytes) return fail(h, LBMD_EINVAL, "get_state: NULL argument");
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
+  const size_t need = state_bytes(h, h->np);
+  if (!buf) {
+    *bytes = need;
+    return LBMD_OK;
+  }
+  if (*bytes < need) {
+    *bytes = need;
+    return fail(h, LBMD_EINVAL, "get_state: buffer too small");
+  }
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  StateHeader hd;
+  std::memset(&hd, 0, sizeof hd);
+  std::memcpy(hd.magic, kStateMagic, sizeof hd.magic);
+  hd.version = kStateVersion;
+  hd.precision = h->p.precision;
+  hd.nx = h->p.nx;
+  hd.ny = h->p.ny;
+  hd.nz = h->p.nz;
+  hd.np = h->np;
+  hd.step = h->step;
+  hd.rho0 = h->p.rho0;
+  char* o = static_cast<char*>(buf);
+  std::memcpy(o, &hd, sizeof hd);
+  o += sizeof hd;
+  const size_t pop = size_t(2) * 19 * size_t(h->N) * h->s_bytes;
+  HIPCHECK(h, hipMemcpyAsync(o, h->f[h->cur], pop, hipMemcpyDeviceToHost, h->stream));
+  o += pop;
+  const size_t vb = 3 * size_t(h->np) * sizeof(double);
+  if (h->np > 0) {
+    const double* src[4] = {h->x, h->v, h->F, h->Fc};
+    for (const double* d : src) {
+      HIPCHECK(h, hipMemcpyAsync(o, d, vb, hipMemcpyDeviceToHost, h->stream));
+      o += vb;
+    }
+    HIPCHECK(h, hipMemcpyAsync(o, h->type, size_t(h->np) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  *bytes = need;
+  return poll_status(h);
+}
+
+int lbmd_set_state(lbmd_handle h, const void* buf, size_t bytes) {
+  if (!h || !buf) return fail(h, LBMD_EINVAL, "set_state: NULL argument");
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
+  if (bytes < sizeof(StateHeader)) return fail(h, LBMD_EINVAL, "set_state: not a state blob");
+  StateHeader hd;
+  std::memcpy(&hd, buf, sizeof hd);
+  if (std::memcmp(hd.magic, kStateMagic, sizeof hd.magic) != 0 || hd.version != kStateVersion)
+    return fail(h, LBMD_EINVAL, "set_state: not a state blob of this version");
+  if (hd.nx != h->p.nx || hd.ny != h->p.ny || hd.nz != h->p.nz || hd.precision != h->p.precision)
+    return fail(h, LBMD_EINVAL, "set_state: lattice size or precision differs from the handle's");
+  if ((h->p.precision == LBMD_FP16DEV || h->p.precision == LBMD_BF16DEV) && hd.rho0 != h->p.rho0)
+    return fail(h, LBMD_EINVAL, "set_state: deviation storage with another rho0");
+  if (hd.np < 0 || hd.np > (int64_t(1) << 28) || hd.step < 0 || bytes < state_bytes(h, hd.np))
+    return fail(h, LBMD_EINVAL, "set_state: truncated or inconsistent blob");
+  const char* in = static_cast<const char*>(buf) + sizeof hd;
+  const size_t pop = size_t(2) * 19 * size_t(h->N) * h->s_bytes;
+  const char* pops = in;
+  in += pop;
+  const size_t vb = 3 * size_t(hd.np) * sizeof(double);
+  const double* x = reinterpret_cast<const double*>(in);
+  const double* v = reinterpret_cast<const double*>(in + vb);
+  const double* F = reinterpret_cast<const double*>(in + 2 * vb);
+  const double* Fc = reinterpret_cast<const double*>(in + 3 * vb);
+  const int32_t* type = reinterpret_cast<const int32_t*>(in + 4 * vb);
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  graph_invalidate(h);
+  // particles: a different count goes through lbmd_set_particles (which
+  // keeps bonds only for an unchanged count); F and F_coup are then restored
+  if (hd.np != h->np) {
+    const bool was_latched = h->latched;
+    h->latched = false;
+    const int rc = lbmd_set_particles(h, hd.np, x, v, type);
+    h->latched = was_latched;
+    if (rc != LBMD_OK) return rc;
+  } else if (hd.np > 0) {
+    for (int64_t i = 0; i < hd.np; ++i)
+      if (type[i] < 0 || type[i] >= h->types.ntypes) return fail(h, LBMD_EINVAL, "set_state: bad particle type");
+    HIPCHECK(h, hipMemcpyAsync(h->x, x, vb, hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(h->v, v, vb, hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(h->type, type, size_t(hd.np) * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  }
+  if (hd.np > 0) {
+    HIPCHECK(h, hipMemcpyAsync(h->F, F, vb, hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(h->Fc, Fc, vb, hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHECK(h, hipMemcpyAsync(h->f[h->cur], pops, pop, hipMemcpyHostToDevice, h->stream));
+  // step index (host count and the device counter the kernels read), a
+  // clear status latch and empty sums
+  const long long never = 0x7fffffffffffffffLL;
+  const int64_t step = hd.step;
+  HIPCHECK(h, hipMemcpyAsync(h->step_dev, &step, sizeof step, hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, hipMemsetAsync(h->status, 0, sizeof(uint32_t), h->stream));
+  HIPCHECK(h, hipMemcpyAsync(h->bad_step, &never, sizeof never, hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, hipMemsetAsync(h->red_out, 0, 8 * sizeof(double), h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  h->step = step;
+  h->latched = false;
+  h->err.clear();
+  state_changed(h);
   return LBMD_OK;
 }
 

@@ -26,7 +26,7 @@ EXPORTS = ["lbmd_create", "lbmd_destroy", "lbmd_set_particles", "lbmd_set_partic
            "lbmd_last_error", "lbmd_set_tiling", "lbmd_kernel_timing", "lbmd_organisation", "lbmd_set_graph",
            "lbmd_autotune", "lbmd_batch_create", "lbmd_batch_destroy", "lbmd_batch_attach", "lbmd_batch_detach",
            "lbmd_batch_step", "lbmd_batch_poll", "lbmd_batch_last_error", "lbmd_set_solvation_lambda",
-           "lbmd_set_mrt", "lbmd_stream_ceiling"]
+           "lbmd_set_mrt", "lbmd_stream_ceiling", "lbmd_get_state", "lbmd_set_state"]
 
 
 class LbmdError(RuntimeError):
@@ -93,6 +93,8 @@ def load():
     L.lbmd_stream_ceiling.argtypes = [H, ctypes.c_int32, _D]
     L.lbmd_set_graph.argtypes = [H, ctypes.c_int32]
     L.lbmd_autotune.argtypes = [H, ctypes.c_int32, ctypes.c_char_p, _I32, _D]
+    L.lbmd_get_state.argtypes = [H, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
+    L.lbmd_set_state.argtypes = [H, ctypes.c_void_p, ctypes.c_size_t]
     L.lbmd_batch_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(H)]
     L.lbmd_batch_destroy.argtypes = [H]
     L.lbmd_batch_attach.argtypes = [H, H, ctypes.c_int64, _I32]
@@ -245,6 +247,23 @@ class Sim:
         x, v, F, Fc = (np.empty((n, 3)) for _ in range(4))
         self._check(load().lbmd_get_particles(self._h, _dp(x), _dp(v), _dp(F), _dp(Fc)))
         return x, v, F, Fc
+
+    def get_state(self):
+        """The dynamic state (populations in stored form, particles, step
+        index) as an opaque uint8 array (lbmd_get_state)."""
+        n = ctypes.c_size_t(0)
+        self._check(load().lbmd_get_state(self._h, None, ctypes.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        rc = load().lbmd_get_state(self._h, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n))
+        if rc not in (OK, EUNSTABLE):
+            self._check(rc)
+        return buf[:n.value]
+
+    def set_state(self, buf):
+        """Replace the dynamic state with one from get_state (lbmd_set_state)."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(load().lbmd_set_state(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+        self.np = int(np.frombuffer(buf[32:40].tobytes(), dtype=np.int64)[0])  # particle count in the blob header
 
     def reductions(self):
         out = np.empty(8)
