@@ -210,6 +210,21 @@ int lbmd_sync(lbmd_handle h);
    status. */
 int lbmd_get_fields(lbmd_handle h, uint32_t mask, double* out, int32_t out_is_device);
 
+/* lbmd_get_fields without any allocation, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc): same arguments, same results.  Its
+   device intermediates -- the density field the export reads for the
+   Shan-Chen force of u, and for a host out the float64 staging of the
+   fields -- live in a static array of LBMD_NOALLOC_SCRATCH_BYTES that the
+   library holds on each GPU it runs on until the process ends; the call
+   makes no hipMalloc or hipFree.  Requests needing more (2 N arithmetic
+   values for the density field, rounded up to 256 bytes, plus 8 bytes per
+   output value for a host out) fail with LBMD_EINVAL.  Every call on one
+   GPU uses that GPU's array: calls that overlap on one GPU (from different
+   handles or threads) race and must be serialised by the caller. */
+#define LBMD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lbmd_get_fields_noalloc(lbmd_handle h, uint32_t mask, double* out, int32_t out_is_device);
+
 /* Host copies of the particle state (any pointer may be NULL): positions,
    velocities, total forces F(n) and their coupling part (friction +
    solvation + random), each [n][3].  Waits.  Returns the latched status. */

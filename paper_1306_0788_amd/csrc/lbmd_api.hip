@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -374,6 +375,38 @@ int autotune(lbmd_ctx* h, int reps, const char* cache_path, int32_t* chosen, dou
   return LBMD_OK;
 }
 
+}  // namespace
+
+namespace {
+// Device scratch of lbmd_get_fields_noalloc: one array per GPU, part of the
+// library's code object, so that the call allocates nothing.  Host code must
+// never pass `scratch` itself to a kernel (in host code it is only a handle
+// of the symbol): the device address comes from hipGetSymbolAddress, once
+// per device, with that device current.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this handle's GPU's scratch array
+int static_scratch(lbmd_ctx* h, void** out) {
+  if (h->device < 0 || h->device >= kMaxDevices) return fail(h, LBMD_EDEVICE, "static scratch: device index");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[h->device]) {
+    int prev = 0;
+    HIPCHECK(h, hipGetDevice(&prev));
+    if (prev != h->device) HIPCHECK(h, hipSetDevice(h->device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != h->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(h, LBMD_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[h->device] = p;
+  }
+  *out = g_scratch_ptr[h->device];
+  return LBMD_OK;
+}
 }  // namespace
 
 namespace {
@@ -764,7 +797,36 @@ int lbmd_get_fields(lbmd_handle h, uint32_t mask, double* out, int32_t out_is_de
     if (int rc = ensure_staging(h, n)) return rc;
     dst = h->export_tmp;
   }
-  HIPCHECK(h, fluid_export(h, mask, dst));
+  HIPCHECK(h, fluid_export(h, mask, dst, h->rho));
+  if (!out_is_device) {
+    HIPCHECK(h, hipMemcpyAsync(out, dst, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+  }
+  return out_is_device ? LBMD_OK : poll_status(h);
+}
+
+int lbmd_get_fields_noalloc(lbmd_handle h, uint32_t mask, double* out, int32_t out_is_device) {
+  if (!h || !out || mask == 0 || (mask & ~(LBMD_RHO | LBMD_U | LBMD_POP)))
+    return fail(h, LBMD_EINVAL, "get_fields_noalloc: bad arguments");
+  if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
+  size_t n = 0;
+  if (mask & LBMD_RHO) n += 2 * h->N;
+  if (mask & LBMD_U) n += 3 * h->N;
+  if (mask & LBMD_POP) n += 38 * h->N;
+  // scratch layout: the density field [2][N], then (host output) the float64
+  // staging of the fields
+  const size_t field = (size_t(2) * h->N * h->c_bytes + 255) & ~size_t(255);
+  const size_t need = field + (out_is_device ? 0 : n * sizeof(double));
+  if (need > kStaticScratchBytes) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "get_fields_noalloc: needs %zu bytes of scratch, more than the static %zu", need,
+             kStaticScratchBytes);
+    return fail(h, LBMD_EINVAL, buf);
+  }
+  void* base = nullptr;
+  if (int rc = static_scratch(h, &base)) return rc;
+  double* dst = out_is_device ? out : reinterpret_cast<double*>(static_cast<char*>(base) + field);
+  HIPCHECK(h, fluid_export(h, mask, dst, base));
   if (!out_is_device) {
     HIPCHECK(h, hipMemcpyAsync(out, dst, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));

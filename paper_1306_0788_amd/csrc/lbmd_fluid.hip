@@ -902,16 +902,18 @@ static hipError_t import_t(lbmd_ctx* h, const double* pop) {
 hipError_t fluid_import(lbmd_ctx* h, const double* pop) { LBMD_BY_STORAGE(import_t, h, pop) }
 
 template <class S>
-static hipError_t export_t(lbmd_ctx* h, uint32_t mask, double* out) {
+static hipError_t export_t(lbmd_ctx* h, uint32_t mask, double* out, void* field) {
   using C = arith_t<S>;
   const S* src = (const S*)h->f[h->cur];
   const FluidConsts<C> K = consts<S>(h);
-  hipLaunchKernelGGL(k_density<S>, plane_grid(h), dim3(256), 0, h->stream, src, (C*)h->rho, h->p.nx, h->p.ny,
+  hipLaunchKernelGGL(k_density<S>, plane_grid(h), dim3(256), 0, h->stream, src, (C*)field, h->p.nx, h->p.ny,
                      h->p.nz, K.rho0);
-  hipLaunchKernelGGL(k_export<S>, plane_grid(h), dim3(256), 0, h->stream, src, (const C*)h->rho, out, K, mask);
+  hipLaunchKernelGGL(k_export<S>, plane_grid(h), dim3(256), 0, h->stream, src, (const C*)field, out, K, mask);
   return hipGetLastError();
 }
-hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out) { LBMD_BY_STORAGE(export_t, h, mask, out) }
+hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out, void* field) {
+  LBMD_BY_STORAGE(export_t, h, mask, out, field)
+}
 
 template <class S>
 static hipError_t pull_copy_t(lbmd_ctx* h) {

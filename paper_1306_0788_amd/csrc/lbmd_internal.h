@@ -396,7 +396,9 @@ hipError_t prof_end(lbmd_ctx* h);
 // launchers (lbmd_fluid.hip)
 hipError_t fluid_init(lbmd_ctx* h, const double* rho_dev);
 hipError_t fluid_import(lbmd_ctx* h, const double* pop_dev);
-hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out_dev);
+// field: [2][N] density-field scratch in the arithmetic type (the export
+// writes it, then reads it for the neighbour sums of u)
+hipError_t fluid_export(lbmd_ctx* h, uint32_t mask, double* out_dev, void* field);
 hipError_t fluid_pull_copy(lbmd_ctx* h);
 hipError_t fluid_pass_a(lbmd_ctx* h);  // moments, SC force, records (+ fused collide)
 hipError_t fluid_pass_b(lbmd_ctx* h);  // collision with the particle force

@@ -26,7 +26,8 @@ EXPORTS = ["lbmd_create", "lbmd_destroy", "lbmd_set_particles", "lbmd_set_partic
            "lbmd_last_error", "lbmd_set_tiling", "lbmd_kernel_timing", "lbmd_organisation", "lbmd_set_graph",
            "lbmd_autotune", "lbmd_batch_create", "lbmd_batch_destroy", "lbmd_batch_attach", "lbmd_batch_detach",
            "lbmd_batch_step", "lbmd_batch_poll", "lbmd_batch_last_error", "lbmd_set_solvation_lambda",
-           "lbmd_set_mrt", "lbmd_stream_ceiling", "lbmd_get_state", "lbmd_set_state"]
+           "lbmd_set_mrt", "lbmd_stream_ceiling", "lbmd_get_state", "lbmd_set_state",
+           "lbmd_get_fields_noalloc"]
 
 
 class LbmdError(RuntimeError):
@@ -93,6 +94,7 @@ def load():
     L.lbmd_stream_ceiling.argtypes = [H, ctypes.c_int32, _D]
     L.lbmd_set_graph.argtypes = [H, ctypes.c_int32]
     L.lbmd_autotune.argtypes = [H, ctypes.c_int32, ctypes.c_char_p, _I32, _D]
+    L.lbmd_get_fields_noalloc.argtypes = [H, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int32]
     L.lbmd_get_state.argtypes = [H, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
     L.lbmd_set_state.argtypes = [H, ctypes.c_void_p, ctypes.c_size_t]
     L.lbmd_batch_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(H)]
@@ -228,6 +230,17 @@ class Sim:
     def get_fields_device(self, mask, out_ptr):
         """Write fields into device memory at out_ptr (e.g. a torch tensor's data_ptr())."""
         self._check(load().lbmd_get_fields(self._h, mask, ctypes.c_void_p(out_ptr), 1))
+
+    def get_fields_noalloc(self, mask, out_ptr=None):
+        """lbmd_get_fields_noalloc: into a new host array, or into device
+        memory at out_ptr."""
+        if out_ptr is not None:
+            self._check(load().lbmd_get_fields_noalloc(self._h, mask, ctypes.c_void_p(out_ptr), 1))
+            return None
+        n = (2 * self.N if mask & RHO else 0) + (3 * self.N if mask & U else 0) + (38 * self.N if mask & POP else 0)
+        out = np.empty(n)
+        self._check(load().lbmd_get_fields_noalloc(self._h, mask, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
 
     def rho(self):
         return self.get_fields(RHO).reshape(2, self.N)
