@@ -307,7 +307,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2_256")
-    ap.add_argument("--kernel", choices=["auto", "fused", "twopass"], default="auto")
+    ap.add_argument("--kernel", choices=["auto", "fused", "twopass", "push"], default="auto")
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default=None,
                     help="population storage (default: the workload's); fp16dev / bf16dev store f - w rho0")
     ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("TILE_Y", "TILE_Z"))
@@ -372,7 +372,8 @@ def main():
     # which the library would replace by a stream of its own)
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    kernel = {"auto": lbmd.KERNEL_AUTO, "fused": lbmd.KERNEL_FUSED, "twopass": lbmd.KERNEL_TWOPASS}[args.kernel]
+    kernel = {"auto": lbmd.KERNEL_AUTO, "fused": lbmd.KERNEL_FUSED, "twopass": lbmd.KERNEL_TWOPASS,
+              "push": lbmd.KERNEL_PUSH}[args.kernel]
     print("bench: setting up %s" % args.workload, file=sys.stderr, flush=True)
     sim, w, npart = setup(args.workload, stream.cuda_stream, kernel, args.tiling, args.precision)
     sim_org = sim.organisation()
@@ -423,7 +424,7 @@ def main():
     alg_bytes = 76 * s_bytes * N
     kavg_s = kms * 1e-3 / max(launches, 1)
     achieved = alg_bytes / kavg_s / 1e9
-    kname = "k_fused" if sim_org == lbmd.KERNEL_FUSED else "k_collide"
+    kname = {lbmd.KERNEL_FUSED: "k_fused", lbmd.KERNEL_TWOPASS: "k_collide", lbmd.KERNEL_PUSH: "k_push"}[sim_org]
     traffic = measured_traffic(kname, label)
     # the same bytes moved by a pass with no arithmetic (one site per
     # thread): what this access pattern reaches on the device
@@ -445,13 +446,16 @@ def main():
         "config": {"workload": label, "lattice": list(w["shape"]), "particles": npart,
                    "storage": prec_name,
                    "forcing": w["forcing"], "kT": w["kT"],
-                   "kernel": "fused" if sim_org == lbmd.KERNEL_FUSED else "twopass",
+                   "kernel": {lbmd.KERNEL_FUSED: "fused", lbmd.KERNEL_TWOPASS: "twopass",
+                              lbmd.KERNEL_PUSH: "push"}[sim_org],
                    "graph": bool(args.graph), "autotuned_tiling": None if tuned is None else list(tuned[:3]),
                    "particle_updates_per_s": round(npart * args.steps / (ms * 1e-3), 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kname,
                      "kernel_ms_avg": round(kavg_s * 1e3, 5), "bytes_per_site": 76 * s_bytes,
+                     "step_achieved": round(alg_bytes / (ms / args.steps * 1e-3) / 1e9, 1),
+                     "step_frac": round(alg_bytes / (ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "pattern_ceiling": round(ceil_gbs, 1), "frac_of_pattern_ceiling": round(achieved / ceil_gbs, 4)},
     }
     sim.close()

@@ -93,7 +93,15 @@ typedef struct lbmd_ctx* lbmd_handle;
                                  stream with the particle force applied
                                  in-line                                      */
 #define LBMD_KERNEL_AUTO 2    /* fused with fewer than one touched node per 128
-                                 sites, two-pass otherwise                    */
+                                 sites, push otherwise (and with MRT)        */
+#define LBMD_KERNEL_PUSH 3    /* one pass over the populations per step: the
+                                 collide + stream pass also accumulates the
+                                 next step's densities and momentum of every
+                                 site from the values it writes (the pulled
+                                 sums of step n+1, Eq. LBMIX), which the next
+                                 step's Shan-Chen force and particle coupling
+                                 read; the particle force is applied in-line.
+                                 Keeps a [3][5][N] moment field.              */
 
 /* lbmd_get_fields masks; outputs are concatenated in this order */
 #define LBMD_RHO 1u /* [2][N] */
@@ -310,8 +318,8 @@ int lbmd_kernel_timing(lbmd_handle h, int32_t enable, double* total_ms, int64_t*
 int lbmd_stream_ceiling(lbmd_handle h, int32_t reps, double* ms);
 
 /* Organisation the next step will use: LBMD_KERNEL_FUSED or
-   LBMD_KERNEL_TWOPASS (resolves LBMD_KERNEL_AUTO); negative on a NULL
-   handle. */
+   LBMD_KERNEL_TWOPASS or LBMD_KERNEL_PUSH (resolves LBMD_KERNEL_AUTO);
+   negative on a NULL handle. */
 int lbmd_organisation(lbmd_handle h);
 
 /* Replay of captured step sequences (default off).  With enable != 0,

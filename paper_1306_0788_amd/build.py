@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmd.so")
-SOURCES = ["lbmd_api.hip", "lbmd_fluid.hip", "lbmd_particles.hip", "lbmd_batch.hip"]
+SOURCES = ["lbmd_api.hip", "lbmd_fluid.hip", "lbmd_push.hip", "lbmd_particles.hip", "lbmd_batch.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",

@@ -50,7 +50,29 @@ void dfree(T*& p) {
 
 // the populations were replaced from outside a step: derived fields kept
 // between steps are stale
-void state_changed(lbmd_ctx* h) { (void)h; }
+void state_changed(lbmd_ctx* h) { h->push_step = -1; }
+
+// moment field of the push organisation and its x-boundary side buffers
+// (allocated on first use): R[3][5][N], H[2][tiles_x][2][5][nz][ny]
+int ensure_push_field(lbmd_ctx* h) {
+  if (h->R && h->H) return LBMD_OK;
+  const size_t tiles_x = size_t(h->p.nx + 63) / 64;
+  if (!h->R) HIPCHECK(h, hipMalloc(&h->R, size_t(3) * 5 * size_t(h->N) * h->c_bytes));
+  if (!h->H) HIPCHECK(h, hipMalloc(&h->H, size_t(2) * tiles_x * 2 * 5 * size_t(h->p.nz) * h->p.ny * h->c_bytes));
+  h->push_step = -1;
+  return LBMD_OK;
+}
+
+// the push organisation's moments of the current step, computed from the
+// populations when the field does not hold them
+int push_ready(lbmd_ctx* h) {
+  if (int rc = ensure_push_field(h)) return rc;
+  if (h->push_step != h->step) {
+    HIPCHECK(h, push_init(h));
+    h->push_step = h->step;
+  }
+  return LBMD_OK;
+}
 
 // drop the captured step sequences (the launch sequence changed)
 void graph_invalidate(lbmd_ctx* h) {
@@ -87,7 +109,8 @@ int validate(const lbmd_params* p, std::string& why) {
   if ((p->precision == LBMD_FP16DEV || p->precision == LBMD_BF16DEV) && !(p->rho0 > 0 && std::isfinite(p->rho0)))
     return why = "deviation storage needs a finite rho0 > 0", LBMD_EINVAL;
   if (p->forcing != LBMD_FORCE_PAPER && p->forcing != LBMD_FORCE_SHIFT) return why = "unknown forcing", LBMD_EINVAL;
-  if (p->kernel != LBMD_KERNEL_FUSED && p->kernel != LBMD_KERNEL_TWOPASS && p->kernel != LBMD_KERNEL_AUTO)
+  if (p->kernel != LBMD_KERNEL_FUSED && p->kernel != LBMD_KERNEL_TWOPASS && p->kernel != LBMD_KERNEL_AUTO &&
+      p->kernel != LBMD_KERNEL_PUSH)
     return why = "unknown kernel", LBMD_EINVAL;
   for (int c = 0; c < 2; ++c)
     if (!(p->tau[c] > 0.5) || !std::isfinite(p->tau[c])) return why = "tau must be > 1/2", LBMD_EINVAL;
@@ -331,6 +354,8 @@ int autotune(lbmd_ctx* h, int reps, const char* cache_path, int32_t* chosen, dou
         }
     }
   }
+  if (org == LBMD_KERNEL_PUSH)
+    if (int rc = push_ready(h)) return rc;
   const bool prof = h->prof_on;
   h->prof_on = false;
   hipEvent_t e0, e1;
@@ -512,6 +537,8 @@ int lbmd_destroy(lbmd_handle h) {
   for (int b = 0; b < 2; ++b)
     if (h->f[b]) (void)hipFree(h->f[b]);
   if (h->rho) (void)hipFree(h->rho);
+  if (h->R) (void)hipFree(h->R);
+  if (h->H) (void)hipFree(h->H);
   if (h->rec) (void)hipFree(h->rec);
   if (h->gP) (void)hipFree(h->gP);
   if (h->gS) (void)hipFree(h->gS);
@@ -753,8 +780,12 @@ int lbmd_step(lbmd_handle h, int64_t nsteps) {
   if (!h || nsteps < 0) return fail(h, LBMD_EINVAL, "step: bad arguments");
   if (h->batch) return fail(h, LBMD_ESTATE, "the handle is attached to a batch");
   if (h->latched) return fail(h, LBMD_ESTATE, "step: a numerical failure is latched");
+  const bool push = organisation_of(h) == LBMD_KERNEL_PUSH;
   int64_t k = 0;
   while (k < nsteps) {
+    // the push organisation reads this step's moments from its field
+    if (push)
+      if (int rc = push_ready(h)) return rc;
     // two steps at a time from a captured graph (the ping-pong parity
     // returns), else one step launched kernel by kernel
     int64_t done = 1;
@@ -769,6 +800,7 @@ int lbmd_step(lbmd_handle h, int64_t nsteps) {
       h->cur = 1 - h->cur;
     }
     const int64_t before = h->step;
+    if (push) h->push_step = h->step + done;
     h->step += done;
     k += done;
     if (h->p.check_every > 0 && h->step / h->p.check_every != before / h->p.check_every)
@@ -990,6 +1022,7 @@ int lbmd_set_tiling(lbmd_handle h, int32_t tile_y, int32_t tile_z, int32_t flags
   h->xcd = flags & LBMD_TILE_XCD ? 1 : 0;
   h->nt = flags & LBMD_TILE_NT ? 1 : 0;
   h->tiling_set = true;
+  h->push_step = -1;  // the push pass clears the face sites of its tiling
   graph_invalidate(h);
   return LBMD_OK;
 }

@@ -204,6 +204,7 @@ int lbmd_batch_attach(lbmd_batch b, lbmd_handle h, int64_t nsteps, int32_t* slot
   b->job[s] = h;
   b->target[s] = h->step + nsteps;
   h->batch = b;
+  h->push_step = -1;  // the batch advances the populations, not the moment field
   b->dirty = true;
   if (slot) *slot = s;
   return LBMD_OK;

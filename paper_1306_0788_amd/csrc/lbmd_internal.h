@@ -252,6 +252,74 @@ __device__ __forceinline__ void load_step(FluidConsts<C>& K) {
                   mix32(uint32_t(uint64_t(K.step) >> 32) ^ mix32(uint32_t(K.seed) ^ uint32_t(K.seed >> 32))));
 }
 
+// ------------------------------------------------------------ moment field
+// Moments of one step for the push organisation: rho_A, rho_B and the raw
+// momentum j of every site, R[q][N] (q = 0..4), plus the contributions that
+// crossed an x boundary of the 64-wide tiles the previous pass used, kept
+// apart so that they could be written without atomics:
+// H[tile][side][q][z][y], side 0 = the column left of the tile, side 1 = the
+// column right of it.  A site in the first column of tile b receives its
+// left neighbour tile's side-1 entry, one in the last column its right
+// neighbour tile's side-0 entry (periodic in the tile index).  Accessed
+// through buffer resources: a 32-bit byte offset per lane and the
+// quantity's offset as a scalar (the field stays below 4 GiB).
+template <class C>
+__device__ __forceinline__ C rsrc_load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  if constexpr (sizeof(C) == 8)
+    return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(r, int(vo), int(so), 0));
+  else
+    return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b32(r, int(vo), int(so), 0));
+}
+template <class C>
+__device__ __forceinline__ void rsrc_store(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, C v) {
+  if constexpr (sizeof(C) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r,
+                                          int(vo), int(so), 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(vo), int(so), 0);
+}
+template <class C>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const C* base, uint64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<C*>(base), (short)0, int(uint32_t(bytes)), 0x00020000);
+}
+
+template <class C>
+struct MomentView {
+  __amdgpu_buffer_rsrc_t R, H;
+  uint32_t qR;     // bytes between quantities of R (N values)
+  uint32_t qH;     // bytes between quantities of a side block (nz * ny values)
+  uint32_t sideH;  // bytes of one side block (5 quantities)
+  int nx, ny, nz, tiles_x;
+  __device__ __forceinline__ C at(int q, int x, int y, int z) const {
+    const uint32_t s = (uint32_t(z) * uint32_t(ny) + uint32_t(y)) * uint32_t(nx) + uint32_t(x);
+    C v = rsrc_load<C>(R, s * uint32_t(sizeof(C)), uint32_t(q) * qR);
+    const int bx = x >> 6, xl = x & 63;
+    const int tw = nx - (bx << 6) < 64 ? nx - (bx << 6) : 64;
+    const uint32_t off = (uint32_t(z) * uint32_t(ny) + uint32_t(y)) * uint32_t(sizeof(C));
+    if (xl == 0)
+      v += rsrc_load<C>(H, off + uint32_t(2 * (bx == 0 ? tiles_x - 1 : bx - 1) + 1) * sideH, uint32_t(q) * qH);
+    if (xl == tw - 1) v += rsrc_load<C>(H, off + uint32_t(2 * (bx == tiles_x - 1 ? 0 : bx + 1)) * sideH, uint32_t(q) * qH);
+    return v;
+  }
+};
+// the view of step `step` into R[3][5][N] and H[2][tiles_x][2][5][nz][ny]
+template <class C>
+__device__ __forceinline__ MomentView<C> moment_view(const C* Rall, const C* Hall, int64_t step, int nx, int ny,
+                                                     int nz, int64_t N) {
+  MomentView<C> v;
+  v.tiles_x = (nx + 63) >> 6;
+  v.qR = uint32_t(N) * uint32_t(sizeof(C));
+  v.qH = uint32_t(nz) * uint32_t(ny) * uint32_t(sizeof(C));
+  v.sideH = 5 * v.qH;
+  v.R = rsrc_of(Rall + int64_t(uint64_t(step) % 3u) * 5 * N, uint64_t(5) * v.qR);
+  v.H = rsrc_of(Hall + int64_t(step & 1) * v.tiles_x * 2 * 5 * int64_t(nz) * ny,
+                uint64_t(v.tiles_x) * 2 * v.sideH);
+  v.nx = nx;
+  v.ny = ny;
+  v.nz = nz;
+  return v;
+}
+
 }  // namespace lbmd
 
 namespace lbmd {
@@ -337,6 +405,9 @@ struct lbmd_ctx {
   int32_t* nflag = nullptr;  // device counter
   int64_t flag_cap = 0;
   void* rec = nullptr;  // [N][16]: N_A(3), N_B(3), u_c(3), rho_A, rho_B at touched nodes
+  void* R = nullptr;    // push organisation: moment field [3][5][N], step n in R[n % 3]
+  void* H = nullptr;    // and its x-boundary terms [2][tiles_x][2][5][nz][ny], step n in H[n % 2]
+  int64_t push_step = -1;  // step whose moments R[step % 3] holds (-1: none)
   void* gP = nullptr;   // [N][4]: particle force density accumulated at nodes
   void* gS = nullptr;   // [N][8]: fluid solvation sums U_A(3), U_B(3) (with lambda only)
 
@@ -403,7 +474,14 @@ hipError_t fluid_pull_copy(lbmd_ctx* h);
 hipError_t fluid_pass_a(lbmd_ctx* h);  // moments, SC force, records (+ fused collide)
 hipError_t fluid_pass_b(lbmd_ctx* h);  // collision with the particle force
 hipError_t finalize_step(lbmd_ctx* h);  // reductions, counters
-int organisation_of(const lbmd_ctx* h);  // LBMD_KERNEL_FUSED or _TWOPASS this step
+int organisation_of(const lbmd_ctx* h);  // LBMD_KERNEL_FUSED, _TWOPASS or _PUSH this step
+// push organisation (lbmd_push.hip)
+struct PushLaunch {
+  int ty, tz, tiles_x, xcd;
+  int64_t nblk;
+};
+hipError_t push_init(lbmd_ctx* h);  // R[step % 3] from the populations, the other two cleared
+hipError_t push_pass(lbmd_ctx* h, const PushLaunch& L);  // collide + stream + next moments
 // launchers (lbmd_particles.hip)
 hipError_t particles_begin(lbmd_ctx* h);  // reduction terms, half kick, drift, flags, cells
 hipError_t particles_mark_sorted(lbmd_ctx* h);  // cell sort done (event for the side stream)

@@ -400,13 +400,17 @@ __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict_
 // hold only the raw momentum (slots 6-8) and the densities (9, 10), as the
 // streaming density pass writes them, and each lane forms its node's
 // neighbour sums N_zeta from the field and u_c = (j + g_SC/2)/rho itself;
-// without it the records are complete (fused organisation).
+// Rall (push organisation; may be null): the moment field [3][5][N] whose
+// buffer step % 3 holds rho_A, rho_B and the raw momentum of every site of
+// this step, used in place of the density field and the records; without
+// either the records are complete (fused organisation).
 constexpr int COUPLE8_BLOCK = 256;
 template <class C>
 __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const double* __restrict__ x,
                                                            const double* __restrict__ v, double* __restrict__ F,
                                                            double* __restrict__ Fc, const int32_t* __restrict__ type,
                                                            const C* __restrict__ rec, const C* __restrict__ rho,
+                                                           const C* __restrict__ Rall, const C* __restrict__ Hall,
                                                            C* __restrict__ gP, C* __restrict__ gS,
                                                            const int32_t* __restrict__ perm, uint32_t* status,
                                                            long long* bad) {
@@ -428,31 +432,39 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
             Z = wrapi(cell_coord(fl[2], A.nz) + oz, A.nz);
   const int64_t nk = (int64_t(Z) * A.ny + Y) * A.nx + X;
   const C* r = rec + nk * 16;
-  // the node's neighbour sums and coupling velocity
-  C NA[3], NB[3], uc[3];
-  if (rho) {
+  // the node's neighbour sums and coupling velocity; ra, rb: its densities
+  C NA[3], NB[3], uc[3], ra, rb;
+  if (rho || Rall) {
+    MomentView<C> mv;
+    if (Rall) mv = moment_view<C>(Rall, Hall, A.step, A.nx, A.ny, A.nz, A.N);
+    // density of component c at (xx, yy, zz): the moment field (push
+    // organisation) or the density field (two-pass)
+    auto dens = [&](int c, int xx, int yy, int zz) -> C {
+      return Rall ? mv.at(c, xx, yy, zz) : rho[c * A.N + (int64_t(zz) * A.ny + yy) * A.nx + xx];
+    };
 #pragma unroll
     for (int a = 0; a < 3; ++a) NA[a] = NB[a] = C(0);
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
       const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
-      const int64_t sn = (int64_t(wrapi(Z + cz, A.nz)) * A.ny + wrapi(Y + cy, A.ny)) * A.nx + wrapi(X + cx, A.nx);
+      const int xx = wrapi(X + cx, A.nx), yy = wrapi(Y + cy, A.ny), zz = wrapi(Z + cz, A.nz);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const C wr = weight<C>(i) * rho[c * A.N + sn];
+        const C wr = weight<C>(i) * dens(c, xx, yy, zz);
         C(&Nc)[3] = c == 0 ? NA : NB;
         if (cx) Nc[0] += cx > 0 ? wr : -wr;
         if (cy) Nc[1] += cy > 0 ? wr : -wr;
         if (cz) Nc[2] += cz > 0 ? wr : -wr;
       }
     }
-    const C ra = r[9], rb = r[10];
+    ra = Rall ? mv.at(0, X, Y, Z) : r[9];
+    rb = Rall ? mv.at(1, X, Y, Z) : r[10];
     const C inv = C(1) / (ra + rb);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const C gsc = -ra * (C(A.G[0][0]) * NA[a] + C(A.G[0][1]) * NB[a]) -
                     rb * (C(A.G[1][0]) * NA[a] + C(A.G[1][1]) * NB[a]);
-      uc[a] = (r[6 + a] + C(0.5) * gsc) * inv;
+      uc[a] = ((Rall ? mv.at(2 + a, X, Y, Z) : r[6 + a]) + C(0.5) * gsc) * inv;
     }
   } else {
 #pragma unroll
@@ -461,6 +473,8 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
       NB[a] = r[3 + a];
       uc[a] = r[6 + a];
     }
+    ra = r[9];
+    rb = r[10];
   }
   double gA[3], gB[3], up[3];
 #pragma unroll
@@ -492,13 +506,12 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
         S[2] += wgt * cz;
       }
     }
-    const double ra = double(r[9]), rb = double(r[10]);
     for (int a = 0; a < 3; ++a) {
       if (on) {
         atomicAdd(&gS[nk * 8 + a], C(la * S[a]));
         atomicAdd(&gS[nk * 8 + 3 + a], C(lb * S[a]));
       }
-      back[a] = group8_sum((la * ra + lb * rb) * S[a]);
+      back[a] = group8_sum((la * double(ra) + lb * double(rb)) * S[a]);
     }
   }
   double fc[3];
@@ -623,16 +636,21 @@ hipError_t particles_forces(lbmd_ctx* h) {
   PartArgs A = args(h);
   // pair forces: added by the second half kick
   const int64_t nb = (h->np + COUPLE8_BLOCK / 8 - 1) / (COUPLE8_BLOCK / 8);
-  // two-pass organisation: records hold j and rho only, the density field is current
-  const void* field = organisation_of(h) == LBMD_KERNEL_TWOPASS ? h->rho : nullptr;
+  // two-pass organisation: records hold j and rho only, the density field is
+  // current; push organisation: the moment field holds both
+  const int org = organisation_of(h);
+  const void* field = org == LBMD_KERNEL_TWOPASS ? h->rho : nullptr;
+  const void* R = org == LBMD_KERNEL_PUSH ? h->R : nullptr;
+  const void* H = org == LBMD_KERNEL_PUSH ? h->H : nullptr;
+  if (org == LBMD_KERNEL_PUSH && (!R || !H)) return hipErrorInvalidValue;  // the field must be allocated
   if (h->p.precision == LBMD_FP64)
     hipLaunchKernelGGL(k_couple8<double>, dim3(nb), dim3(COUPLE8_BLOCK), 0, h->stream, A, h->x, h->v, h->F, h->Fc,
-                       h->type, (const double*)h->rec, (const double*)field, (double*)h->gP, (double*)h->gS,
-                       h->cell_perm, h->status, h->bad_step);
+                       h->type, (const double*)h->rec, (const double*)field, (const double*)R, (const double*)H,
+                       (double*)h->gP, (double*)h->gS, h->cell_perm, h->status, h->bad_step);
   else
     hipLaunchKernelGGL(k_couple8<float>, dim3(nb), dim3(COUPLE8_BLOCK), 0, h->stream, A, h->x, h->v, h->F, h->Fc,
-                       h->type, (const float*)h->rec, (const float*)field, (float*)h->gP, (float*)h->gS,
-                       h->cell_perm, h->status, h->bad_step);
+                       h->type, (const float*)h->rec, (const float*)field, (const float*)R, (const float*)H,
+                       (float*)h->gP, (float*)h->gS, h->cell_perm, h->status, h->bad_step);
   return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ LIBPATH = os.path.join(_HERE, "liblbmd.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32, FP16DEV, BF16DEV = 0, 1, 2, 3
 FORCE_PAPER, FORCE_SHIFT = 0, 1
-KERNEL_FUSED, KERNEL_TWOPASS, KERNEL_AUTO = 0, 1, 2
+KERNEL_FUSED, KERNEL_TWOPASS, KERNEL_AUTO, KERNEL_PUSH = 0, 1, 2, 3
 RHO, U, POP = 1, 2, 4
 PAIR_WCA, PAIR_DH, BOND_FENE = 0, 1, 2
 MAX_TYPES = 8

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 FP64, FP32 = lbmd.FP64, lbmd.FP32
 PAPER, SHIFT = lbmd.FORCE_PAPER, lbmd.FORCE_SHIFT
-FUSED, TWOPASS = lbmd.KERNEL_FUSED, lbmd.KERNEL_TWOPASS
+FUSED, TWOPASS, PUSH = lbmd.KERNEL_FUSED, lbmd.KERNEL_TWOPASS, lbmd.KERNEL_PUSH
 
 
 def run_pair(case, steps):
@@ -32,7 +32,7 @@ def run_pair(case, steps):
 
 @pytest.mark.parametrize("precision,tol", [(FP64, 1e-12), (FP32, 1e-5)])
 @pytest.mark.parametrize("forcing", [PAPER, SHIFT])
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_one_step_32cubed(precision, tol, forcing, kernel):
     """The 32^3 mixture with 64 particles (G_AB = 1.6, gamma = 0.5)."""
     c = Case((32, 32, 32), precision, forcing, kernel, G=1.6, gamma=0.5, vel_amp=0.02,
@@ -41,7 +41,7 @@ def test_one_step_32cubed(precision, tol, forcing, kernel):
     compare(c, g, o, tol, tol, "1 step")
 
 
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_hundred_steps_fp64_paper(kernel):
     """The 32^3 workload, 100 steps, paper forcing (G rho = 1.6 is above the
     spinodal: round-off grows by about 40x per 100 steps)."""
@@ -58,7 +58,7 @@ def test_velocity_shift_error_growth_fp64():
     compare(c, g, o, 1e-9, 1e-9, "20 steps shift")
 
 
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_hundred_steps_fp32_density(kernel):
     """FP32 storage, 100 steps: densities within 1e-4 of the FP64 oracle."""
     c = Case((32, 32, 32), FP32, PAPER, kernel, G=1.6, gamma=0.5, mass=(1.0,))
@@ -68,7 +68,7 @@ def test_hundred_steps_fp32_density(kernel):
 
 
 @pytest.mark.parametrize("shape", [(37, 29, 23), (3, 3, 3), (4, 5, 6), (70, 3, 5), (65, 9, 17), (1, 7, 9)])
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_ragged_shapes(shape, kernel):
     n = 6 if np.prod(shape) < 200 else 40
     c = Case(shape, FP64, PAPER, kernel, G=1.3, gamma=0.7, npart=n, vel_amp=0.02, kappa=((0.2, 0.1),),
@@ -79,7 +79,7 @@ def test_ragged_shapes(shape, kernel):
 
 @pytest.mark.parametrize("tiling", [(2, 1, 1, 1), (4, 3, 0, 1), (8, 5, 1, 0), (8, 7, 0, 0), (16, 40, 1, 1),
                                     (16, 2, 0, 1)])
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_tilings_agree(tiling, kernel):
     c = Case((37, 29, 23), FP64, PAPER, kernel, G=1.3, gamma=0.7, npart=40, vel_amp=0.02, tiling=tiling)
     g, o = run_pair(c, 3)
@@ -87,7 +87,7 @@ def test_tilings_agree(tiling, kernel):
 
 
 @pytest.mark.parametrize("precision,tol", [(FP64, 1e-12), (FP32, 1e-5)])
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_fluctuating_identical_draws(precision, tol, kernel):
     """kT > 0: both sides draw the same Philox4x32-10 normals for the fluid modes
     and the particle random force."""
@@ -98,38 +98,41 @@ def test_fluctuating_identical_draws(precision, tol, kernel):
 
 
 @pytest.mark.parametrize("precision,tol", [(FP64, 1e-11), (FP32, 1e-5)])
-def test_chains_fene_wca_debye_hueckel(precision, tol):
+@pytest.mark.parametrize("kernel", [FUSED, PUSH])
+def test_chains_fene_wca_debye_hueckel(precision, tol, kernel):
     """Bead-spring chains (FENE + WCA + screened Debye-Hueckel, all beads
     charged), solvation on A, fluctuating fluid: the polyelectrolyte set-up at
     a small box."""
-    c = Case((24, 24, 24), precision, PAPER, FUSED, G=1.8, gamma=1.0, kT=1e-4, seed=3, chains=(6, 20),
+    c = Case((24, 24, 24), precision, PAPER, kernel, G=1.8, gamma=1.0, kT=1e-4, seed=3, chains=(6, 20),
              kappa=((0.1, 0.0),), mass=(2000.0,), charge=(1.0,), wca=(1.0, 1.0), fene=(30.0, 1.5),
              dh=(1.0, 3.0, 1.0))
     g, o = run_pair(c, 4)
     compare(c, g, o, tol, tol, "chains")
 
 
-def test_particles_on_nodes_edges_and_shared_cells():
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
+def test_particles_on_nodes_edges_and_shared_cells(kernel):
     L = 12
     pos = [[3.0, 4.0, 5.0], [0.0, 0.0, 0.0], [L - 1e-13, 2.5, 7.25], [6.5, 6.5, 6.5], [6.6, 6.4, 6.55],
            [6.45, 6.52, 6.51], [11.999999, 11.999999, 0.0]]
-    c = Case((L, L, L), FP64, PAPER, FUSED, G=1.2, gamma=0.9, positions=pos, vel_amp=0.05,
+    c = Case((L, L, L), FP64, PAPER, kernel, G=1.2, gamma=0.9, positions=pos, vel_amp=0.05,
              kappa=((0.4, -0.3),), mass=(50.0,))
     g, o = run_pair(c, 6)
     compare(c, g, o, 1e-11, 1e-11, "edges")
 
 
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_no_particles(kernel):
     c = Case((33, 17, 12), FP32, PAPER, kernel, G=1.5, npart=0)
     g, o = run_pair(c, 4)
     compare(c, g, o, 1e-5, 1e-5, "no particles")
 
 
-def test_invariants_on_gpu():
+@pytest.mark.parametrize("kernel", [FUSED, PUSH])
+def test_invariants_on_gpu(kernel):
     """Per-component mass to round-off and the fluid + particle momentum
     invariant, read from the device reductions."""
-    c = Case((24, 20, 16), FP64, PAPER, FUSED, G=1.4, gamma=0.8, npart=50, vel_amp=0.05,
+    c = Case((24, 20, 16), FP64, PAPER, kernel, G=1.4, gamma=0.8, npart=50, vel_amp=0.05,
              kappa=((0.3, -0.1),), mass=(400.0,), wca=(1.0, 0.05), min_dist=1.3)
     g = c.gpu_sim()
     first = None
@@ -180,7 +183,7 @@ def test_invalid_parameters_rejected():
         s.set_particles([[1.0, np.nan, 2.0]])
 
 
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_stepping_on_after_a_failure_stays_in_bounds(kernel):
     """Regression: after a numerical failure the particle velocities diverge
     before they turn non-finite, and positions far outside the box once gave
@@ -198,7 +201,7 @@ def test_stepping_on_after_a_failure_stays_in_bounds(kernel):
 
 
 @pytest.mark.parametrize("precision,tol", [(FP64, 1e-11), (FP32, 1e-5)])
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_fluid_solvation_force(precision, tol, kernel):
     """The fluid solvation force (lambda per type and component) with its
     momentum return, next to friction and kappa solvation, two particle
@@ -209,7 +212,7 @@ def test_fluid_solvation_force(precision, tol, kernel):
     compare(c, g, o, tol * 5, tol * 5, "lambda")
 
 
-@pytest.mark.parametrize("kernel", [FUSED, TWOPASS])
+@pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_invariant_with_fluid_solvation_on_gpu(kernel):
     """Fluid raw momentum + sum (m v + F_c/2) stays constant on the GPU with
     friction, kappa and lambda solvation (FP64; both organisations: the fused
@@ -235,13 +238,14 @@ MRT = (-1.3, -0.8, -1.1, -1.6)  # bulk, shear, momentum, kinetic eigenvalues
 
 
 @pytest.mark.parametrize("precision,tol", [(FP64, 1e-11), (FP32, 1e-5)])
-def test_mrt_with_particles(precision, tol):
+@pytest.mark.parametrize("kernel", [lbmd.KERNEL_AUTO, TWOPASS])
+def test_mrt_with_particles(precision, tol, kernel):
     """Distinct eigenvalues for the four mode groups, the general forcing
     source term, particles with kappa and lambda solvation: 5 steps."""
-    c = Case((30, 20, 14), precision, PAPER, lbmd.KERNEL_AUTO, G=1.3, gamma=0.6, npart=40, vel_amp=0.03,
+    c = Case((30, 20, 14), precision, PAPER, kernel, G=1.3, gamma=0.6, npart=40, vel_amp=0.03,
              kappa=((0.2, -0.1),), mass=(20.0,), lambda_fs=((0.05, -0.02),), mrt=MRT)
     g, o = run_pair(c, 5)
-    assert g.organisation() == TWOPASS
+    assert g.organisation() == (PUSH if kernel == lbmd.KERNEL_AUTO else TWOPASS)
     compare(c, g, o, tol * 5, tol * 5, "mrt")
 
 
@@ -255,12 +259,13 @@ def test_mrt_fluctuating_identical_draws(precision, tol):
     compare(c, g, o, tol * 10, tol * 10, "mrt noise")
 
 
-def test_mrt_reduces_to_bgk():
+@pytest.mark.parametrize("kernel", [TWOPASS, PUSH])
+def test_mrt_reduces_to_bgk(kernel):
     """All four eigenvalues -1/tau give the BGK step (up to rounding)."""
     tau = 0.8
-    c1 = Case((18, 14, 12), FP64, PAPER, TWOPASS, G=1.3, tau=tau, gamma=0.5, npart=20, vel_amp=0.02,
+    c1 = Case((18, 14, 12), FP64, PAPER, kernel, G=1.3, tau=tau, gamma=0.5, npart=20, vel_amp=0.02,
               kappa=((0.2, -0.1),), mass=(5.0,), mrt=(-1 / tau,) * 4)
-    c0 = Case((18, 14, 12), FP64, PAPER, TWOPASS, G=1.3, tau=tau, gamma=0.5, npart=20, vel_amp=0.02,
+    c0 = Case((18, 14, 12), FP64, PAPER, kernel, G=1.3, tau=tau, gamma=0.5, npart=20, vel_amp=0.02,
               kappa=((0.2, -0.1),), mass=(5.0,))
     a, b = c1.gpu_sim(), c0.gpu_sim()
     a.step(6)
@@ -278,3 +283,19 @@ def test_mrt_rejects_bad_eigenvalues():
     f = lbmd.Sim((8, 8, 8), kernel=FUSED)
     with pytest.raises(lbmd.LbmdError):
         f.set_mrt(MRT)
+
+
+@pytest.mark.parametrize("shape,tiling", [((130, 37, 29), (4, 5, 1, 1)), ((128, 12, 10), (2, 3, 0, 1)),
+                                          ((64, 17, 6), (8, 1, 0, 0)), ((65, 9, 40), (16, 7, 1, 1))])
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-11), (FP32, 1e-5)])
+def test_push_moments_across_box_faces_edges_and_corners(shape, tiling, precision, tol):
+    """The push organisation forms each step's densities and momentum from
+    the previous step's post-collision values, adding the contributions of
+    neighbouring boxes at box faces, edges and corners; many boxes in every
+    direction (full 64-lane tiles, a 1-lane tail, one-plane chunks), 8 steps
+    with particles against the oracle."""
+    c = Case(shape, precision, PAPER, PUSH, G=1.4, gamma=0.7, npart=60, vel_amp=0.02, kappa=((0.2, 0.1),),
+             mass=(3.0,), amp=0.03, tiling=tiling)
+    g, o = run_pair(c, 8)
+    assert g.organisation() == PUSH
+    compare(c, g, o, tol * 8, tol * 8, "push boxes %s %s" % (shape, tiling))

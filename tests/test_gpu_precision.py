@@ -56,7 +56,7 @@ def run(case, steps):
 
 
 @pytest.mark.parametrize("precision", [FP16DEV, BF16DEV])
-@pytest.mark.parametrize("kernel", [lbmd.KERNEL_FUSED, lbmd.KERNEL_TWOPASS])
+@pytest.mark.parametrize("kernel", [lbmd.KERNEL_FUSED, lbmd.KERNEL_TWOPASS, lbmd.KERNEL_PUSH])
 def test_one_step_against_oracle(precision, kernel):
     """The 32^3 mixture with 64 moving particles, one step."""
     G = 1.6
@@ -91,7 +91,7 @@ def test_ragged_shapes(shape, precision):
 
 
 @pytest.mark.parametrize("precision,growth", [(FP16DEV, 100.0), (BF16DEV, 100.0)])
-@pytest.mark.parametrize("kernel", [lbmd.KERNEL_FUSED, lbmd.KERNEL_TWOPASS])
+@pytest.mark.parametrize("kernel", [lbmd.KERNEL_FUSED, lbmd.KERNEL_TWOPASS, lbmd.KERNEL_PUSH])
 def test_hundred_steps_density(precision, growth, kernel):
     """Densities after 100 steps at G = 1.6 (above the spinodal): within the
     one-step bound times the growth of the unstable modes over 100 steps
