@@ -299,6 +299,66 @@ def serving(njobs, rate, seed, max_jobs, mem_gib, one_by_one, jobs):
     return out
 
 
+def run_workload(name, stream, kernel, tiling, precision, autotune, cache, graph, warmup, steps):
+    """Set up workload `name` on `stream`, tune its tiling (unless told not
+    to), take `warmup` untimed steps, then time `steps` steps between HIP
+    events on the stream, with the collide-stream kernel's launches timed
+    by events of their own (eager launches; with graph replay those are
+    taken over the warm-up instead).  Returns the measurements, or None after
+    a numerical failure."""
+    import torch
+    from paper_1306_0788_amd import lbmd
+    print("bench: setting up %s" % name, file=sys.stderr, flush=True)
+    sim, w, npart = setup(name, stream.cuda_stream, kernel, tiling, precision)
+    sim_org = sim.organisation()
+    tuned = None
+    if autotune:
+        print("bench: autotuning the tiling", file=sys.stderr, flush=True)
+        tuned = sim.autotune(reps=3, cache_path=cache)
+    if graph:
+        sim.set_graph(True)
+    N = int(np.prod(w["shape"]))
+    prec_name = precision or w["precision"]
+    s_bytes = STORAGE_BYTES[prec_name]
+    label = name if prec_name == w["precision"] else "%s_%s" % (name, prec_name)
+    print("bench: %s warmup %d steps" % (name, warmup), file=sys.stderr, flush=True)
+    first = min(2, warmup)
+    sim.step(first)
+    if graph:
+        sim.kernel_timing(True)
+    sim.step(warmup - first)
+    torch.cuda.synchronize()
+    if graph:
+        kms, launches = sim.kernel_timing(False)
+    assert sim.sync() == lbmd.OK, sim.last_error()
+    if not graph:
+        sim.kernel_timing(True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    sim.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    if not graph:
+        kms, launches = sim.kernel_timing(False)
+    st = sim.sync()
+    if st != lbmd.OK:
+        print("bench: %s numerical failure: %s" % (name, sim.last_error()), file=sys.stderr)
+        sim.close()
+        return None
+    print("bench: %s timed %d steps in %.3f ms" % (name, steps, ms), file=sys.stderr, flush=True)
+    kname = {lbmd.KERNEL_FUSED: "k_fused", lbmd.KERNEL_TWOPASS: "k_collide", lbmd.KERNEL_PUSH: "k_push"}[sim_org]
+    # the same bytes moved by a pass with no arithmetic (one site per
+    # thread): what this access pattern reaches on the device
+    ceil_gbs = 76 * s_bytes * N / (sim.stream_ceiling(10) * 1e-3) / 1e9
+    sim.close()
+    del sim
+    return dict(ms=ms, N=N, npart=npart, w=w, prec=prec_name, s_bytes=s_bytes, label=label, org=sim_org,
+                tuned=tuned, kname=kname, kernel_ms=kms / max(launches, 1), ceiling_gbs=ceil_gbs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,6 +379,9 @@ def main():
     ap.add_argument("--autotune-cache", default=None, metavar="PATH",
                     help="tiling cache file: a run that finds its key there skips the timing (profiling runs use "
                          "the tiling an earlier run chose, without the candidates' launches in their traces)")
+    ap.add_argument("--also", nargs="*", default=["c3"], metavar="WORKLOAD",
+                    help="further workloads timed the same way and reported as keys of the line (default: the "
+                         "256^3 bead-spring workload c3)")
     ap.add_argument("--serve-jobs", type=int, default=512, help="jobs in the served Poisson stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=32)
@@ -374,61 +437,19 @@ def main():
     torch.cuda.set_stream(stream)
     kernel = {"auto": lbmd.KERNEL_AUTO, "fused": lbmd.KERNEL_FUSED, "twopass": lbmd.KERNEL_TWOPASS,
               "push": lbmd.KERNEL_PUSH}[args.kernel]
-    print("bench: setting up %s" % args.workload, file=sys.stderr, flush=True)
-    sim, w, npart = setup(args.workload, stream.cuda_stream, kernel, args.tiling, args.precision)
-    sim_org = sim.organisation()
-    tuned = None
-    if args.autotune:
-        print("bench: autotuning the tiling", file=sys.stderr, flush=True)
-        tuned = sim.autotune(reps=3, cache_path=args.autotune_cache)
-    if args.graph:
-        sim.set_graph(True)
-    N = int(np.prod(w["shape"]))
-    prec_name = args.precision or w["precision"]
-    s_bytes = STORAGE_BYTES[prec_name]
-    label = args.workload if prec_name == w["precision"] else "%s_%s" % (args.workload, prec_name)
-
-    print("bench: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
-    # With graph replay the timed steps run without per-kernel events (event
-    # timing forces eager launches), so the dominant kernel is timed over the
-    # eager warmup steps after the first two instead.
-    first = min(2, args.warmup)
-    sim.step(first)
-    if args.graph:
-        sim.kernel_timing(True)
-    sim.step(args.warmup - first)
-    torch.cuda.synchronize()
-    if args.graph:
-        kms, launches = sim.kernel_timing(False)
-    assert sim.sync() == lbmd.OK, sim.last_error()
-
-    if not args.graph:
-        sim.kernel_timing(True)
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    sim.step(args.steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
-    if not args.graph:
-        kms, launches = sim.kernel_timing(False)
-    st = sim.sync()
-    if st != lbmd.OK:
-        print("bench: numerical failure: %s" % sim.last_error(), file=sys.stderr)
+    r = run_workload(args.workload, stream, kernel, args.tiling, args.precision, args.autotune,
+                     args.autotune_cache, args.graph, args.warmup, args.steps)
+    if r is None:
         sys.exit(1)
-    print("bench: timed %d steps in %.3f ms" % (args.steps, ms), file=sys.stderr, flush=True)
-
+    ms, N, npart, w, prec_name, s_bytes, label = r["ms"], r["N"], r["npart"], r["w"], r["prec"], r["s_bytes"], \
+        r["label"]
+    sim_org, tuned, kname = r["org"], r["tuned"], r["kname"]
     mlups = N * args.steps / (ms * 1e-3) / 1e6
     alg_bytes = 76 * s_bytes * N
-    kavg_s = kms * 1e-3 / max(launches, 1)
+    kavg_s = r["kernel_ms"] * 1e-3
     achieved = alg_bytes / kavg_s / 1e9
-    kname = {lbmd.KERNEL_FUSED: "k_fused", lbmd.KERNEL_TWOPASS: "k_collide", lbmd.KERNEL_PUSH: "k_push"}[sim_org]
     traffic = measured_traffic(kname, label)
-    # the same bytes moved by a pass with no arithmetic (one site per
-    # thread): what this access pattern reaches on the device
-    ceil_gbs = alg_bytes / (sim.stream_ceiling(10) * 1e-3) / 1e9
+    ceil_gbs = r["ceiling_gbs"]
     line = {
         "metric": "MLUPS (2-component D3Q19 Shan-Chen + coupled particles, one full step)",
         "value": round(mlups, 2),
@@ -458,8 +479,26 @@ def main():
                      "step_frac": round(alg_bytes / (ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "pattern_ceiling": round(ceil_gbs, 1), "frac_of_pattern_ceiling": round(achieved / ceil_gbs, 4)},
     }
-    sim.close()
-    del sim
+    for extra in args.also:
+        # further workloads, timed the same way (own warm-up and window below
+        # their recorded onset), reported as keys of the same line
+        wx = workloads.WORKLOADS[extra]
+        onx = wx.get("onset")
+        kx = 70 if onx is None else min(70, onx - 5 - args.warmup)
+        rx = run_workload(extra, stream, lbmd.KERNEL_AUTO, None, None, args.autotune, args.autotune_cache,
+                          args.graph, args.warmup, kx)
+        if rx is None:
+            line[extra] = {"failed": True}
+            continue
+        bx = 76 * rx["s_bytes"] * rx["N"]
+        line[extra] = {"MLUPS": round(rx["N"] * kx / (rx["ms"] * 1e-3) / 1e6, 2), "steps": kx,
+                       "ms_per_step": round(rx["ms"] / kx, 5), "lattice": list(rx["w"]["shape"]),
+                       "particles": rx["npart"], "kT": rx["w"]["kT"], "kernel": rx["kname"],
+                       "kernel_ms_avg": round(rx["kernel_ms"], 5),
+                       "kernel_frac": round(bx / (rx["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "step_frac": round(bx / (rx["ms"] / kx * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "autotuned_tiling": None if rx["tuned"] is None else list(rx["tuned"][:3]),
+                       "particle_updates_per_s": round(rx["npart"] * kx / (rx["ms"] * 1e-3), 1)}
     if jobs is not None:
         line["served"] = serving(args.serve_jobs, args.serve_rate, 5, args.serve_slots, args.serve_mem_gib,
                                  args.serve_one_by_one, jobs)

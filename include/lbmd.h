@@ -93,7 +93,9 @@ typedef struct lbmd_ctx* lbmd_handle;
                                  stream with the particle force applied
                                  in-line                                      */
 #define LBMD_KERNEL_AUTO 2    /* fused with fewer than one touched node per 128
-                                 sites, push otherwise (and with MRT)        */
+                                 sites; otherwise (and always with MRT) push
+                                 for a deterministic fluid and two-pass with
+                                 thermal noise                               */
 #define LBMD_KERNEL_PUSH 3    /* one pass over the populations per step: the
                                  collide + stream pass also accumulates the
                                  next step's densities and momentum of every
@@ -172,9 +174,10 @@ int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, 
    lambda_shear and the nine kinetic modes with lambda_ghost (each in
    (-2, 0); BGK is every eigenvalue -1/tau), in place of the BGK relaxation
    with tau[].  Fluctuations (kT > 0) take each mode's own eigenvalue.  Needs
-   LBMD_FORCE_PAPER; the step then uses the two-pass organisation (a kernel
-   explicitly set to LBMD_KERNEL_FUSED is refused).  enable = 0 returns to
-   BGK.  Errors: LBMD_EINVAL, LBMD_ESTATE (in a batch). */
+   LBMD_FORCE_PAPER; the step then uses the two-pass or the push
+   organisation (LBMD_KERNEL_AUTO: push without noise, two-pass with it; a
+   kernel explicitly set to LBMD_KERNEL_FUSED is refused).  enable = 0
+   returns to BGK.  Errors: LBMD_EINVAL, LBMD_ESTATE (in a batch). */
 int lbmd_set_mrt(lbmd_handle h, int32_t enable, double lambda_bulk, double lambda_shear, double lambda_mom,
                  double lambda_ghost);
 

@@ -157,6 +157,7 @@ void free_particles(lbmd_ctx* h) {
   dfree(h->cell_of);
   dfree(h->rank_of);
   dfree(h->cell_perm);
+  dfree(h->xs);
   dfree(h->flag_list);
   dfree(h->red_part);
   h->np_cap = 0;
@@ -257,6 +258,9 @@ int enqueue_step(lbmd_ctx* h) {
   if (parts) {
     HIPCHECK(h, particles_pairs(h));
     HIPCHECK(h, particles_forces(h));
+    // the pair forces (side stream, beside the coupling) are joined before
+    // the collide-stream pass, which then has the chip to itself
+    HIPCHECK(h, particles_join_pairs(h));
   }
   HIPCHECK(h, fluid_pass_b(h));
   if (parts) HIPCHECK(h, particles_end(h));
@@ -342,6 +346,7 @@ int autotune(lbmd_ctx* h, int reps, const char* cache_path, int32_t* chosen, dou
   for (int a = 0; a < 3; ++a) {
     const int ty = fused ? tys_f[a] : tys_t[a];
     if (ty > std::max(2, h->p.ny) && ty != 2) continue;
+    if (org == LBMD_KERNEL_PUSH && ty > push_rows_max(h)) continue;
     const int ntz = fused ? 3 : 4;
     for (int b = 0; b < ntz; ++b) {
       const int tz = std::min(fused ? tzs_f[b] : tzs_t[b], h->p.nz);
@@ -603,6 +608,7 @@ int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double
     HIPCHECK(h, dalloc(&h->cell_of, n));
     HIPCHECK(h, dalloc(&h->rank_of, n));
     HIPCHECK(h, dalloc(&h->cell_perm, n));
+    HIPCHECK(h, dalloc(&h->xs, 4 * n));
     HIPCHECK(h, dalloc(&h->flag_list, 8 * n));
     HIPCHECK(h, dalloc(&h->red_part, 3 * ((n + 255) / 256)));
     h->np_cap = n;
@@ -656,7 +662,7 @@ int lbmd_set_mrt(lbmd_handle h, int32_t enable, double lambda_bulk, double lambd
     for (double v : l)
       if (!(v > -2.0 && v < 0.0)) return fail(h, LBMD_EINVAL, "set_mrt: every eigenvalue must lie in (-2, 0)");
     if (h->p.forcing != LBMD_FORCE_PAPER) return fail(h, LBMD_EINVAL, "set_mrt: needs the paper's forcing");
-    if (h->p.kernel == LBMD_KERNEL_FUSED) return fail(h, LBMD_EINVAL, "set_mrt: MRT runs in the two-pass organisation");
+    if (h->p.kernel == LBMD_KERNEL_FUSED) return fail(h, LBMD_EINVAL, "set_mrt: MRT runs in the two-pass or push organisation");
   }
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   graph_invalidate(h);

@@ -274,9 +274,9 @@ __device__ __forceinline__ void fused_tile(const S* __restrict__ src_, S* __rest
       C NA[3], NB[3];
       nsum_ring<C, TY>(ring, k & 3, (k + 1) & 3, (k + 2) & 3, wv, lane, NA, NB);
       const int64_t s = z * plane + int64_t(y) * nx + x;
-      const C gp[3] = {0, 0, 0};
+      const C gp[3] = {0, 0, 0}, gu[6] = {0, 0, 0, 0, 0, 0};
       if (!HOLD) pull<S, C>(src, x, y, z, nx, ny, nz, cur);
-      const Macro<C> m = macro<C, FORCING>(cur, NA, NB, gp, K);
+      const Macro<C> m = macro<C, FORCING>(cur, NA, NB, gp, K, gu, false);
       if (mask && ((mask[s >> 5] >> (s & 31)) & 1u)) {
         C uc[3];
         coupling_velocity<C, FORCING>(m, uc);
@@ -347,13 +347,13 @@ __device__ __forceinline__ void fix_node(const S* __restrict__ src, S* __restric
     gP[s * GPS + a] = C(0);
   }
   mask[s >> 5] = 0u;
-  C gu[6];
+  C gu[6] = {0, 0, 0, 0, 0, 0};
   if (gS)
     for (int q = 0; q < 6; ++q) {
       gu[q] = gS[s * GSS + q];
       gS[s * GSS + q] = C(0);
     }
-  collide<C, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s), gS ? gu : nullptr);
+  collide<C, FORCING, NOISE>(f, NA, NB, gp, K, uint32_t(s), gu, gS != nullptr);
   store<S, C>(make_pops<S>(dst, N, K.rho0, K.srkey), uint32_t(s), f);
 }
 
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(64 * TY) void k_collide(const S* __restrict__ src_,
           }
         }
       }
-      const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K, fs ? gu : nullptr);
+      const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K, gu, fs);
       relax_site<C, FORCING, NOISE, MRT>(f, m, K, uint32_t(s));
       store<S, C, NOISE || Storage<S>::deviation>(dst, uint32_t(s), f, K.nt);
     }
@@ -609,13 +609,19 @@ hipError_t fluid_pull_copy(lbmd_ctx* h) { LBMD_BY_STORAGE(pull_copy_t, h) }
 
 // organisation actually used this step
 static int organisation(const lbmd_ctx* h) {
+  // with thermal noise the push kernel's in-block gather comes on top of
+  // the per-site normals; its collide pass then runs longer than the
+  // density pass it saves (bead-spring chains at 256^3: 2.39 against
+  // 2.26 ms per step), so fluctuating steps use the two-pass organisation
+  const int many = h->p.kT > 0.0 ? LBMD_KERNEL_TWOPASS : LBMD_KERNEL_PUSH;
   // the MRT collision is built into the two-pass and push kernels only
-  if (h->mrt) return h->p.kernel == LBMD_KERNEL_TWOPASS ? LBMD_KERNEL_TWOPASS : LBMD_KERNEL_PUSH;
+  if (h->mrt)
+    return h->p.kernel == LBMD_KERNEL_TWOPASS || h->p.kernel == LBMD_KERNEL_PUSH ? h->p.kernel : many;
   if (h->p.kernel != LBMD_KERNEL_AUTO) return h->p.kernel;
   // the fused pass re-collides every touched node with scattered accesses
   // (about 76 per node); the push pass writes and reads a five-value moment
   // field per site.  Break-even near one touched node per 128 sites.
-  return (h->np == 0 || 8 * h->np * 128 < h->N) ? LBMD_KERNEL_FUSED : LBMD_KERNEL_PUSH;
+  return (h->np == 0 || 8 * h->np * 128 < h->N) ? LBMD_KERNEL_FUSED : many;
 }
 
 struct Launch {
@@ -655,8 +661,7 @@ static Launch tiles(lbmd_ctx* h) {
   Launch L;
   L.tiles_x = (h->p.nx + 63) / 64;
   L.ty = h->tile_y;
-  // the push kernel's LDS (density ring and row exchange) caps FP64 at 8 rows
-  if (org == LBMD_KERNEL_PUSH && h->p.precision == LBMD_FP64 && L.ty > 8) L.ty = 8;
+  if (org == LBMD_KERNEL_PUSH && L.ty > push_rows_max(h)) L.ty = push_rows_max(h);
   const int tiles_y = (h->p.ny + L.ty - 1) / L.ty;
   L.tz = std::max(1, std::min(h->tile_z, h->p.nz));
   L.nblk = int64_t(L.tiles_x) * tiles_y * ((h->p.nz + L.tz - 1) / L.tz);

@@ -214,11 +214,11 @@ struct PartArgs {
   double gamma, kT;
   double G[2][2];        // Shan-Chen coupling matrix (node records formed in the coupling kernel)
   uint64_t seed;
-  int64_t step;          // set from *stepp by the kernels that need it
   const int64_t* stepp;  // device step counter
   ParticleTypes T;
   PairParams pp;
   int ncell[3];
+  double rcut;  // largest non-bonded cut-off (cells farther than it are skipped)
   int use_cells;
   int build_list;  // append touched nodes to the compact list (fused organisation)
 };
@@ -417,6 +417,7 @@ struct lbmd_ctx {
   double* Fcons = nullptr;  // conservative forces of the step being taken
   int32_t* type = nullptr;
   int32_t* cell_of = nullptr;  // pair-force cell of each particle
+  double* xs = nullptr;        // [n][4] positions and charges in cell order (pair forces)
   int32_t* rank_of = nullptr;  // arrival rank inside its cell
   lbmd::ParticleTypes types;
   lbmd::PairParams pair;
@@ -447,7 +448,7 @@ struct lbmd_ctx {
   std::string err;
 
   lbmd_batch_s* batch = nullptr;  // attached to a multi-lattice batch
-  bool mrt = false;                // MRT collision (two-pass organisation)
+  bool mrt = false;                // MRT collision (two-pass and push organisations)
   double mrt_lam[4] = {0, 0, 0, 0};  // momentum, bulk, shear, kinetic
 
   // replay of captured two-step sequences, one per ping-pong parity
@@ -481,11 +482,19 @@ struct PushLaunch {
   int64_t nblk;
 };
 hipError_t push_init(lbmd_ctx* h);  // R[step % 3] from the populations, the other two cleared
+// most rows per tile of the push kernel: 16 only for the deterministic BGK
+// step with 4-byte arithmetic (FP64's LDS ring and row exchange do not fit
+// 160 KiB at 16 rows; the fluctuating and MRT kernels need about 190
+// registers, which 1,024 threads per block cannot have)
+inline int push_rows_max(const lbmd_ctx* h) {
+  return h->p.precision == LBMD_FP64 || h->p.kT > 0.0 || h->mrt ? 8 : 16;
+}
 hipError_t push_pass(lbmd_ctx* h, const PushLaunch& L);  // collide + stream + next moments
 // launchers (lbmd_particles.hip)
 hipError_t particles_begin(lbmd_ctx* h);  // reduction terms, half kick, drift, flags, cells
 hipError_t particles_mark_sorted(lbmd_ctx* h);  // cell sort done (event for the side stream)
 hipError_t particles_pairs(lbmd_ctx* h);  // conservative forces (side stream)
+hipError_t particles_join_pairs(lbmd_ctx* h);  // main stream waits for them
 hipError_t particles_forces(lbmd_ctx* h); // coupling forces, total force, spread
 hipError_t particles_end(lbmd_ctx* h);    // second half kick
 }  // namespace lbmd

@@ -194,10 +194,20 @@ __global__ void k_scan_add(int32_t* __restrict__ start, int32_t* __restrict__ cn
   }
 }
 
+// cell-sorted order: perm[k] = particle at sorted position k, and xs[k] =
+// its position and charge, so that a neighbour cell's particles are read as
+// one contiguous run
 __global__ void k_scatter(const int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank_of,
-                          const int32_t* __restrict__ start, int32_t* __restrict__ perm, int64_t np) {
+                          const int32_t* __restrict__ start, int32_t* __restrict__ perm, const double* __restrict__ x,
+                          const int32_t* __restrict__ type, ParticleTypes T, double* __restrict__ xs, int64_t np) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p < np) perm[start[cell_of[p]] + rank_of[p]] = int32_t(p);
+  if (p >= np) return;
+  const int64_t k = start[cell_of[p]] + rank_of[p];
+  perm[k] = int32_t(p);
+  xs[4 * k] = x[3 * p];
+  xs[4 * k + 1] = x[3 * p + 1];
+  xs[4 * k + 2] = x[3 * p + 2];
+  xs[4 * k + 3] = T.charge[type[p]];
 }
 
 __device__ __forceinline__ void add_radial(double fr, const double (&d)[3], double r, double (&Fp)[3]) {
@@ -216,71 +226,97 @@ __device__ __forceinline__ double group8_sum(double v) {
   return v;
 }
 
-// Pair and bond forces with 8 lanes per particle: lane l takes the
-// neighbour cells (and bonds) whose running index is l mod 8, and the
-// group sums the 8 partial forces.  The particle's force is the same sum
-// of pair terms in another order.
+// Pair and bond forces, one thread per particle in cell order (neighbouring
+// threads share cells).  The cells of one x row are consecutive in the
+// sorted order, so each (y, z) row of neighbour cells is one contiguous run
+// of xs; rows and columns of cells whose nearest face lies beyond the
+// cut-off from the particle are skipped (the face distance is measured in
+// FP64 with a margin, so no pair inside the cut-off is lost).  The force on
+// a particle is the sum of its pair terms, each evaluated exactly as before.
 constexpr int PAIRS_BLOCK = 256;
 __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double* __restrict__ x,
                                                        const int32_t* __restrict__ type,
                                                        const int32_t* __restrict__ cell_start,
                                                        const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ cell_of,
+                                                       const double* __restrict__ xs,
                                                        const int32_t* __restrict__ bstart,
                                                        const int32_t* __restrict__ bnbr, double* __restrict__ Fcons) {
-  const int64_t tid = int64_t(blockIdx.x) * (PAIRS_BLOCK / 8) + (threadIdx.x >> 3);
-  const int l = threadIdx.x & 7;
-  // every lane of a group takes part in the final sum; a group past the last
-  // particle works on the last one and writes nothing
-  const bool on = tid < A.np;
-  const int64_t tc = on ? tid : A.np - 1;
-  // particles in cell order: neighbouring groups share cells
-  const int64_t p = A.use_cells ? int64_t(perm[tc]) : tc;
-  const int t = type[p];
+  const int64_t k = int64_t(blockIdx.x) * PAIRS_BLOCK + threadIdx.x;  // sorted position
+  if (k >= A.np) return;
+  const int64_t p = A.use_cells ? int64_t(perm[k]) : k;
   const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
   double Fp[3] = {0, 0, 0};
   const double L[3] = {double(A.nx), double(A.ny), double(A.nz)};
   if (A.use_cells) {
     const int c = cell_of[p];
-    const int cx = c % A.ncell[0], cy = (c / A.ncell[0]) % A.ncell[1], cz = c / (A.ncell[0] * A.ncell[1]);
-    const int lo[3] = {A.ncell[0] >= 3 ? -1 : 0, A.ncell[1] >= 3 ? -1 : 0, A.ncell[2] >= 3 ? -1 : 0};
-    const int hi[3] = {A.ncell[0] >= 3 ? 1 : 0, A.ncell[1] >= 3 ? 1 : 0, A.ncell[2] >= 3 ? 1 : 0};
-    const double qp = A.T.charge[t];
-    // this lane's cell ranges first (independent loads), then the pairs
-    int rb[4], re[4], nr = 0;
-    int idx = 0;
+    const int cc[3] = {c % A.ncell[0], (c / A.ncell[0]) % A.ncell[1], c / (A.ncell[0] * A.ncell[1])};
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (A.ncell[a] < 3) {  // the whole (periodic) axis is one cell row
+        lo[a] = 0;
+        hi[a] = 0;
+        continue;
+      }
+      const double edge = L[a] / A.ncell[a];
+      const double off = xp[a] - cc[a] * edge;  // distance to the cell's lower face
+      const double margin = 1e-9 * L[a];
+      lo[a] = off < A.rcut + margin ? -1 : 0;
+      hi[a] = edge - off < A.rcut + margin ? 1 : 0;
+    }
+    const double qp = A.T.charge[type[p]];
     for (int dz = lo[2]; dz <= hi[2]; ++dz)
-      for (int dy = lo[1]; dy <= hi[1]; ++dy)
-        for (int dx = lo[0]; dx <= hi[0]; ++dx, ++idx) {
-          if ((idx & 7) != l) continue;
-          const int nc = (wrapi(cz + dz, A.ncell[2]) * A.ncell[1] + wrapi(cy + dy, A.ncell[1])) * A.ncell[0] +
-                         wrapi(cx + dx, A.ncell[0]);
-          rb[nr] = cell_start[nc];
-          re[nr] = cell_start[nc + 1];
-          ++nr;
+      for (int dy = lo[1]; dy <= hi[1]; ++dy) {
+        const int zc = wrapi(cc[2] + dz, A.ncell[2]), yc = wrapi(cc[1] + dy, A.ncell[1]);
+        const int row = (zc * A.ncell[1] + yc) * A.ncell[0];
+        // the x run of cells cc[0] + lo .. cc[0] + hi, split where it wraps
+        int x0 = cc[0] + lo[0], x1 = cc[0] + hi[0];
+        int runs[2][2], nr = 0;
+        if (A.ncell[0] < 3) {
+          runs[0][0] = row;
+          runs[0][1] = row + A.ncell[0];
+          nr = 1;
+        } else if (x0 < 0) {
+          runs[0][0] = row + A.ncell[0] - 1;
+          runs[0][1] = row + A.ncell[0];
+          runs[1][0] = row;
+          runs[1][1] = row + x1 + 1;
+          nr = 2;
+        } else if (x1 >= A.ncell[0]) {
+          runs[0][0] = row + x0;
+          runs[0][1] = row + A.ncell[0];
+          runs[1][0] = row;
+          runs[1][1] = row + 1;
+          nr = 2;
+        } else {
+          runs[0][0] = row + x0;
+          runs[0][1] = row + x1 + 1;
+          nr = 1;
         }
-    for (int rr = 0; rr < nr; ++rr) {
-      for (int jj = rb[rr]; jj < re[rr]; ++jj) {
-        const int q = perm[jj];
-        if (q == p) continue;
-        double d[3];
-        for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
-        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        const double r = sqrt(r2);
-        if (A.pp.wca_on && r2 < A.pp.wca_rc2) {
-          const double s2 = A.pp.wca_sigma * A.pp.wca_sigma / r2;
-          const double s6 = s2 * s2 * s2;
-          add_radial(24.0 * A.pp.wca_eps * (2.0 * s6 * s6 - s6) / r, d, r, Fp);
-        }
-        if (A.pp.dh_on && r < A.pp.dh_rc) {
-          const double qq = qp * A.T.charge[type[q]];
-          add_radial(qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) / r2, d, r, Fp);
+        for (int rr = 0; rr < nr; ++rr) {
+          const int jb = cell_start[runs[rr][0]], je = cell_start[runs[rr][1]];
+          for (int jj = jb; jj < je; ++jj) {
+            if (jj == k) continue;
+            double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = min_image(xs[4 * jj + a] - xp[a], L[a]);
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const double r = sqrt(r2);
+            if (A.pp.wca_on && r2 < A.pp.wca_rc2) {
+              const double s2 = A.pp.wca_sigma * A.pp.wca_sigma / r2;
+              const double s6 = s2 * s2 * s2;
+              add_radial(24.0 * A.pp.wca_eps * (2.0 * s6 * s6 - s6) / r, d, r, Fp);
+            }
+            if (A.pp.dh_on && r < A.pp.dh_rc) {
+              const double qq = qp * xs[4 * jj + 3];
+              add_radial(qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) / r2, d, r, Fp);
+            }
+          }
         }
       }
-    }
   }
   if (A.pp.fene_on && bstart) {
-    for (int jj = bstart[p] + l; jj < bstart[p + 1]; jj += 8) {
+    for (int jj = bstart[p]; jj < bstart[p + 1]; ++jj) {
       const int q = bnbr[jj];
       double d[3];
       for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
@@ -290,10 +326,7 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
       add_radial(fr, d, r, Fp);
     }
   }
-  for (int a = 0; a < 3; ++a) {
-    const double Fa = group8_sum(Fp[a]);
-    if (on && l == 0) Fcons[3 * p + a] = Fa;
-  }
+  for (int a = 0; a < 3; ++a) Fcons[3 * p + a] = Fp[a];
 }
 
 // Coupling force: trilinear interpolation of u_c and the lattice density
@@ -346,7 +379,7 @@ __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict_
                                            const int32_t* __restrict__ perm, uint32_t* status, long long* bad,
                                            int64_t tid) {
   if (tid >= A.np) return;
-  A.step = *A.stepp;
+  const int64_t step = *A.stepp;  // a local: writing into A would copy it to scratch
   const int64_t p = A.use_cells ? int64_t(perm[tid]) : tid;
   const int t = type[p];
   const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
@@ -365,7 +398,7 @@ __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict_
   }
   double R[4] = {0, 0, 0, 0};
   if (A.kT > 0.0) {
-    normals4<double>(A.seed, A.step, uint32_t(p), 0u, 1u, R);
+    normals4<double>(A.seed, step, uint32_t(p), 0u, 1u, R);
     const double amp = sqrt(2.0 * A.kT * A.gamma);
     for (int a = 0; a < 3; ++a) R[a] *= amp;
   }
@@ -380,7 +413,7 @@ __device__ __forceinline__ void couple_one(PartArgs A, const double* __restrict_
     F[3 * p + a] = Ft;
     ok = ok && isfinite(Ft);
   }
-  if (!ok) flag_unstable(status, bad, 2u, A.step);
+  if (!ok) flag_unstable(status, bad, 2u, step);
   // the interpolated part goes back to the fluid by the same interpolation
 #pragma unroll
   for (int k = 0; k < 8; ++k)
@@ -420,7 +453,7 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
   // particle works on the last one and writes nothing
   const bool on = tid < A.np;
   const int64_t tc = on ? tid : A.np - 1;
-  A.step = *A.stepp;
+  const int64_t step = *A.stepp;  // a local: writing into A would copy it to scratch
   const int64_t p = A.use_cells ? int64_t(perm[tc]) : tc;
   const int t = type[p];
   const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
@@ -436,7 +469,7 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
   C NA[3], NB[3], uc[3], ra, rb;
   if (rho || Rall) {
     MomentView<C> mv;
-    if (Rall) mv = moment_view<C>(Rall, Hall, A.step, A.nx, A.ny, A.nz, A.N);
+    if (Rall) mv = moment_view<C>(Rall, Hall, step, A.nx, A.ny, A.nz, A.N);
     // density of component c at (xx, yy, zz): the moment field (push
     // organisation) or the density field (two-pass)
     auto dens = [&](int c, int xx, int yy, int zz) -> C {
@@ -485,7 +518,7 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
   }
   double R[4] = {0, 0, 0, 0};
   if (A.kT > 0.0) {
-    normals4<double>(A.seed, A.step, uint32_t(p), 0u, 1u, R);
+    normals4<double>(A.seed, step, uint32_t(p), 0u, 1u, R);
     const double amp = sqrt(2.0 * A.kT * A.gamma);
     for (int a = 0; a < 3; ++a) R[a] *= amp;
   }
@@ -525,7 +558,7 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
     }
     ok = ok && isfinite(Ft);
   }
-  if (on && k == 0 && !ok) flag_unstable(status, bad, 2u, A.step);
+  if (on && k == 0 && !ok) flag_unstable(status, bad, 2u, step);
   // the interpolated part goes back to the fluid by the same interpolation
   if (on)
     for (int a = 0; a < 3; ++a) atomicAdd(&gP[nk * 4 + a], C(-Wk * fc[a]));
@@ -539,7 +572,7 @@ __device__ __forceinline__ void end_one(PartArgs A, const double* __restrict__ x
                                         const int32_t* __restrict__ type, uint32_t* status, long long* bad,
                                         int64_t p) {
   if (p >= A.np) return;
-  A.step = *A.stepp;
+  const int64_t step = *A.stepp;  // a local: writing into A would copy it to scratch
   const double m = A.T.mass[type[p]];
   bool ok = true;
   for (int a = 0; a < 3; ++a) {
@@ -552,7 +585,7 @@ __device__ __forceinline__ void end_one(PartArgs A, const double* __restrict__ x
     v[3 * p + a] = vn;
     ok = ok && isfinite(Ft) && isfinite(vn) && isfinite(x[3 * p + a]);
   }
-  if (!ok) flag_unstable(status, bad, 2u, A.step);
+  if (!ok) flag_unstable(status, bad, 2u, step);
 }
 
 __global__ void k_end(PartArgs A, const double* __restrict__ x, double* __restrict__ v, double* __restrict__ F,
@@ -574,11 +607,11 @@ static PartArgs args(const lbmd_ctx* h) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) A.G[a][b] = h->p.G[a][b];
   A.seed = h->p.seed;
-  A.step = 0;
   A.stepp = h->step_dev;
   A.T = h->types;
   A.pp = h->pair;
   for (int a = 0; a < 3; ++a) A.ncell[a] = h->ncell[a];
+  A.rcut = h->rcut;
   A.use_cells = (h->pair.wca_on || h->pair.dh_on) ? 1 : 0;
   A.build_list = organisation_of(h) == LBMD_KERNEL_FUSED ? 1 : 0;
   return A;
@@ -599,7 +632,7 @@ hipError_t particles_begin(lbmd_ctx* h) {
     hipLaunchKernelGGL(k_scan_add, dim3((n + 1 + 255) / 256), dim3(256), 0, h->stream, h->cell_start, h->cell_count,
                        h->scan_block, n + 1);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, h->stream, h->cell_of, h->rank_of, h->cell_start,
-                       h->cell_perm, h->np);
+                       h->cell_perm, h->x, h->type, h->types, h->xs, h->np);
   }
   return hipGetLastError();
 }
@@ -609,13 +642,10 @@ bool has_conservative(const lbmd_ctx* h) {
 }
 
 // Conservative forces on the side stream, ordered after the kick/drift/cell
-// sort on the main stream (particles_mark_sorted records that point); the
-// main stream waits for them only before the second half kick, so they run
-// beside the density pass, the coupling and the collide pass.  The density
-// pass is enqueued between the two calls, so it is dispatched first and
-// gets the whole chip in its first wave of blocks, with the pair forces
-// filling in beside it (also in a captured graph, whose nodes follow the
-// enqueue order).
+// sort on the main stream (particles_mark_sorted records that point); they
+// run beside the coupling kernel (and the density pass of the two-pass
+// organisation), and the main stream waits for them before the
+// collide-stream pass.
 hipError_t particles_mark_sorted(lbmd_ctx* h) {
   if (!has_conservative(h)) return hipSuccess;
   return hipEventRecord(h->ev_sorted, h->stream);
@@ -625,11 +655,16 @@ hipError_t particles_pairs(lbmd_ctx* h) {
   if (!has_conservative(h)) return hipSuccess;
   PartArgs A = args(h);
   if (hipError_t e = hipStreamWaitEvent(h->side, h->ev_sorted, 0)) return e;
-  const int64_t nb = (h->np + PAIRS_BLOCK / 8 - 1) / (PAIRS_BLOCK / 8);
+  const int64_t nb = (h->np + PAIRS_BLOCK - 1) / PAIRS_BLOCK;
   hipLaunchKernelGGL(k_pairs, dim3(nb), dim3(PAIRS_BLOCK), 0, h->side, A, h->x, h->type, h->cell_start, h->cell_perm,
-                     h->cell_of, h->bond_start, h->bond_nbr, h->Fcons);
+                     h->cell_of, h->xs, h->bond_start, h->bond_nbr, h->Fcons);
   if (hipError_t e = hipGetLastError()) return e;
   return hipEventRecord(h->ev_pairs, h->side);
+}
+
+hipError_t particles_join_pairs(lbmd_ctx* h) {
+  if (!has_conservative(h)) return hipSuccess;
+  return hipStreamWaitEvent(h->stream, h->ev_pairs, 0);
 }
 
 hipError_t particles_forces(lbmd_ctx* h) {
@@ -656,9 +691,7 @@ hipError_t particles_forces(lbmd_ctx* h) {
 
 hipError_t particles_end(lbmd_ctx* h) {
   PartArgs A = args(h);
-  const bool cons = has_conservative(h);
-  if (cons)
-    if (hipError_t e = hipStreamWaitEvent(h->stream, h->ev_pairs, 0)) return e;
+  const bool cons = has_conservative(h);  // joined before the collide-stream pass
   hipLaunchKernelGGL(k_end, dim3((h->np + 255) / 256), dim3(256), 0, h->stream, A, h->x, h->v, h->F,
                      cons ? (const double*)h->Fcons : nullptr, h->type, h->status, h->bad_step);
   return hipGetLastError();

@@ -142,8 +142,17 @@ __device__ __forceinline__ void add_group(C (&A)[RQ], C TA, C TB, C X) {
   if (CZ < 0) A[4] -= TA + TB;
 }
 
+// Occupancy: the deterministic BGK step with 4-byte arithmetic is held to
+// 128 registers (4 waves per SIMD); the fluctuating and MRT steps (about 190
+// registers) and FP64 run at 2 waves per SIMD and at most 8 rows, so that
+// they are not squeezed into spills.
+template <class S, bool NOISE, bool MRT>
+constexpr int push_min_waves() {
+  return sizeof(arith_t<S>) == 4 && !NOISE && !MRT ? 4 : 2;
+}
+
 template <class S, int TY, int FORCING, bool NOISE, bool MRT>
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(sizeof(arith_t<S>) == 4 ? 4 : 2, 8)))
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(push_min_waves<S, NOISE, MRT>(), 8)))
 void k_push(const S* __restrict__ src_, S* __restrict__ dst_, arith_t<S>* __restrict__ Rall,
             FluidConsts<arith_t<S>> K, int tz, int tiles_x, int xcd, const uint32_t* __restrict__ mask,
             arith_t<S>* __restrict__ gP, arith_t<S>* __restrict__ gS, arith_t<S>* __restrict__ Hall,
@@ -294,7 +303,7 @@ void k_push(const S* __restrict__ src_, S* __restrict__ dst_, arith_t<S>* __rest
           }
         }
       }
-      const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K, fs ? gu : nullptr);
+      const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K, gu, fs);
       {
         SiteOut<C> o;
         o.rho[0] = m.rho[0];
@@ -378,23 +387,30 @@ void k_push(const S* __restrict__ src_, S* __restrict__ dst_, arith_t<S>* __rest
       }
     }
     // the columns left and right of the box: the velocities leaving through
-    // x (several waves add to one entry)
+    // x (several waves add to one entry).  The left-moving and right-moving
+    // velocity of each (c_y, c_z) pair go out of lanes 0 and twv-1 in the
+    // same instructions; a one-column tile sends both from lane 0.
     if (T.inside && (lane == 0 || lane == twv - 1)) {
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        if (lane != (side == 0 ? 0 : twv - 1)) continue;
-#pragma unroll
-        for (int i = 1; i < 19; ++i) {
-          if (D3Q19::cx[i] != (side == 0 ? -1 : 1)) continue;
-          const int r = wv + 1 + D3Q19::cy[i];
-          const int sl = D3Q19::cz[i] > 0 ? slp : (D3Q19::cz[i] < 0 ? slm : sl0);
-          const C a = f[0][i], b = f[1][i];
-          atomicAdd(&scol[side][sl][r][0], a);
-          atomicAdd(&scol[side][sl][r][1], b);
-          atomicAdd(&scol[side][sl][r][2], side == 0 ? -(a + b) : a + b);
-          if (D3Q19::cy[i] != 0) atomicAdd(&scol[side][sl][r][3], D3Q19::cy[i] > 0 ? a + b : -(a + b));
-          if (D3Q19::cz[i] != 0) atomicAdd(&scol[side][sl][r][4], D3Q19::cz[i] > 0 ? a + b : -(a + b));
-        }
+      auto out = [&](int side, int il, int ir, int cy, int cz) {
+        const C a = side == 0 ? f[0][il] : f[0][ir], b = side == 0 ? f[1][il] : f[1][ir], t = a + b;
+        const int r = wv + 1 + cy;
+        const int sl = cz > 0 ? slp : (cz < 0 ? slm : sl0);
+        atomicAdd(&scol[side][sl][r][0], a);
+        atomicAdd(&scol[side][sl][r][1], b);
+        atomicAdd(&scol[side][sl][r][2], side == 0 ? -t : t);
+        if (cy != 0) atomicAdd(&scol[side][sl][r][3], cy > 0 ? t : -t);
+        if (cz != 0) atomicAdd(&scol[side][sl][r][4], cz > 0 ? t : -t);
+      };
+      const int npass = twv == 1 ? 2 : 1;
+      for (int pass = 0; pass < npass; ++pass) {
+        const int side = twv == 1 ? pass : (lane == 0 ? 0 : 1);
+        // (left, right) velocity pairs: (-1,0,0)/(1,0,0), (-1,-1,0)/(1,-1,0),
+        // (-1,1,0)/(1,1,0), (-1,0,-1)/(1,0,-1), (-1,0,1)/(1,0,1)
+        out(side, 2, 1, 0, 0);
+        out(side, 8, 9, -1, 0);
+        out(side, 10, 7, 1, 0);
+        out(side, 12, 13, 0, -1);
+        out(side, 14, 11, 0, 1);
       }
     }
     __syncthreads();
@@ -466,21 +482,26 @@ static hipError_t push_launch(lbmd_ctx* h, const PushLaunch& L) {
   return hipGetLastError();
 }
 
+// 16 rows exist only for the deterministic BGK step with 4-byte arithmetic
+// (push_rows_max); the tiling clamps the others to 8
 template <class S, int TY>
 static hipError_t push_by_physics(lbmd_ctx* h, const PushLaunch& L) {
   if (h->p.forcing == LBMD_FORCE_SHIFT) return push_launch<S, TY, LBMD_FORCE_SHIFT, false, false>(h, L);
   const bool noise = h->p.kT > 0.0;
-  if (h->mrt)
-    return noise ? push_launch<S, TY, LBMD_FORCE_PAPER, true, true>(h, L)
-                 : push_launch<S, TY, LBMD_FORCE_PAPER, false, true>(h, L);
-  return noise ? push_launch<S, TY, LBMD_FORCE_PAPER, true, false>(h, L)
-               : push_launch<S, TY, LBMD_FORCE_PAPER, false, false>(h, L);
+  if constexpr (TY <= 8) {
+    if (h->mrt)
+      return noise ? push_launch<S, TY, LBMD_FORCE_PAPER, true, true>(h, L)
+                   : push_launch<S, TY, LBMD_FORCE_PAPER, false, true>(h, L);
+    if (noise) return push_launch<S, TY, LBMD_FORCE_PAPER, true, false>(h, L);
+  } else {
+    if (h->mrt || noise) return hipErrorInvalidConfiguration;
+  }
+  return push_launch<S, TY, LBMD_FORCE_PAPER, false, false>(h, L);
 }
 
-// rows per tile; FP64 stops at 8 (16 rows of its LDS ring and row exchange
-// would not fit the 160 KiB of a workgroup; the tiling clamps it)
 template <class S>
 static hipError_t push_by_rows(lbmd_ctx* h, const PushLaunch& L) {
+  if (L.ty > push_rows_max(h)) return hipErrorInvalidConfiguration;
   switch (L.ty) {
     case 2: return push_by_physics<S, 2>(h, L);
     case 4: return push_by_physics<S, 4>(h, L);

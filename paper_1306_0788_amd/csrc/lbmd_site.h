@@ -184,12 +184,14 @@ struct Macro {
 
 // NA, NB: neighbour sums N_zeta = sum_i w_i rho_zeta(r+c_i) c_i;
 // gp: total particle force density at the node
-// gu (may be null): the fluid solvation sums U_zeta = sum_p lambda_zeta S_p
-// at the node, [2][3]; the force on component zeta is -rho_zeta U_zeta
-// (Sec. 2, Eq. solvation_lambda)
+// gu (used when fs is set): the fluid solvation sums U_zeta = sum_p
+// lambda_zeta S_p at the node, [2][3]; the force on component zeta is
+// -rho_zeta U_zeta (Sec. 2, Eq. solvation_lambda).  A register array and a
+// flag rather than a pointer that may be null: a pointer to a local array
+// would put the array in scratch memory.
 template <class C, int FORCING>
 __device__ __forceinline__ Macro<C> macro(const C (&f)[2][19], const C (&NA)[3], const C (&NB)[3],
-                                          const C (&gp)[3], const FluidConsts<C>& K, const C* gu = nullptr){
+                                          const C (&gp)[3], const FluidConsts<C>& K, const C (&gu)[6], bool fs) {
   Macro<C> m;
   C jc[2][3];
   moments_pairs<C>(f[0], m.rho[0], jc[0]);
@@ -205,7 +207,7 @@ __device__ __forceinline__ Macro<C> macro(const C (&f)[2][19], const C (&NA)[3],
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       m.g[c][a] = -m.rho[c] * (K.G[c][0] * NA[a] + K.G[c][1] * NB[a]) + frac * gp[a] -
-                  (gu ? m.rho[c] * gu[3 * c + a] : C(0));
+                  (fs ? m.rho[c] * gu[3 * c + a] : C(0));
   }
   if (FORCING == LBMD_FORCE_PAPER) {
     // barycentric velocity with half the total force (Appendix, u and
@@ -290,8 +292,8 @@ __device__ __forceinline__ void relax_site(C (&f)[2][19], const Macro<C>& m, con
 template <class C, int FORCING, bool NOISE>
 __device__ __forceinline__ SiteOut<C> collide(C (&f)[2][19], const C (&NA)[3], const C (&NB)[3],
                                               const C (&gp)[3], const FluidConsts<C>& K, uint32_t site,
-                                              const C* gu = nullptr) {
-  const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K, gu);
+                                              const C (&gu)[6], bool fs) {
+  const Macro<C> m = macro<C, FORCING>(f, NA, NB, gp, K, gu, fs);
   relax_site<C, FORCING, NOISE>(f, m, K, site);
   SiteOut<C> o;
   o.rho[0] = m.rho[0];

@@ -250,12 +250,16 @@ def test_mrt_with_particles(precision, tol, kernel):
 
 
 @pytest.mark.parametrize("precision,tol", [(FP64, 1e-11), (FP32, 1e-5)])
-def test_mrt_fluctuating_identical_draws(precision, tol):
+@pytest.mark.parametrize("kernel,tiling", [(lbmd.KERNEL_AUTO, None), (PUSH, None), (PUSH, (16, 4, 0, 0, 1))])
+def test_mrt_fluctuating_identical_draws(precision, tol, kernel, tiling):
     """kT > 0 under MRT: each mode's noise amplitude follows its own
-    eigenvalue; the same Philox draws on both sides."""
-    c = Case((20, 18, 16), precision, PAPER, lbmd.KERNEL_AUTO, G=1.2, gamma=1.0, kT=1e-4, seed=11, npart=30,
-             kappa=((0.1, 0.0),), mass=(5.0,), mrt=MRT)
+    eigenvalue; the same Philox draws on both sides.  Automatic choice
+    (two-pass with noise) and the push kernel, also with 16 rows requested
+    (the fluctuating push kernel has at most 8)."""
+    c = Case((20, 18, 16), precision, PAPER, kernel, G=1.2, gamma=1.0, kT=1e-4, seed=11, npart=30,
+             kappa=((0.1, 0.0),), mass=(5.0,), mrt=MRT, tiling=tiling)
     g, o = run_pair(c, 3)
+    assert g.organisation() == (TWOPASS if kernel == lbmd.KERNEL_AUTO else PUSH)
     compare(c, g, o, tol * 10, tol * 10, "mrt noise")
 
 
