@@ -221,6 +221,7 @@ struct PartArgs {
   double rcut;  // largest non-bonded cut-off (cells farther than it are skipped)
   int use_cells;
   int build_list;  // append touched nodes to the compact list (fused organisation)
+  int mark_in_couple;  // the coupling kernel marks the touched nodes (push organisation)
 };
 
 // Scalar parameters of one fluid step, passed by value to the kernels.

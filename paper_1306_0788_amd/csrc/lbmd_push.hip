@@ -94,19 +94,20 @@ __global__ __launch_bounds__(RINIT_BLOCK) void k_rinit(const S* __restrict__ src
 // value of the lane upstream in x (dx = +1: lane - 1, dx = -1: lane + 1);
 // zero where that lane lies outside the 64-wide tile.  A whole-wave DPP
 // shift (wave_shr:1 / wave_shl:1): a plain vector move, no LDS round trip.
+// The edge lane (0 for wave_shr, 63 for wave_shl) has no source lane: with
+// bound_ctrl it is written with zero (and the old value is zero as well), so
+// no select is needed.
 __device__ __forceinline__ uint32_t lane_shift(uint32_t v, int dx) {
   return dx > 0 ? uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xf, 0xf, true))
                 : uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x130, 0xf, 0xf, true));
 }
-__device__ __forceinline__ float from_lane(float v, int dx, int lane) {
-  const float r = __builtin_bit_cast(float, lane_shift(__builtin_bit_cast(uint32_t, v), dx));
-  return (dx > 0 ? lane == 0 : lane == 63) ? 0.0f : r;
+__device__ __forceinline__ float from_lane(float v, int dx, int) {
+  return __builtin_bit_cast(float, lane_shift(__builtin_bit_cast(uint32_t, v), dx));
 }
-__device__ __forceinline__ double from_lane(double v, int dx, int lane) {
+__device__ __forceinline__ double from_lane(double v, int dx, int) {
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
   const uint64_t lo = lane_shift(uint32_t(b), dx), hi = lane_shift(uint32_t(b >> 32), dx);
-  const double r = __builtin_bit_cast(double, lo | (hi << 32));
-  return (dx > 0 ? lane == 0 : lane == 63) ? 0.0 : r;
+  return __builtin_bit_cast(double, lo | (hi << 32));
 }
 
 // In-tile sums of the velocities with (c_y, c_z) = (CY, CZ) that arrive in
@@ -312,11 +313,12 @@ void k_push(const S* __restrict__ src_, S* __restrict__ dst_, arith_t<S>* __rest
         o.j[1] = m.j[1];
         o.j[2] = m.j[2];
         if (!moments_ok(o)) flag_unstable(status, bad, 1u, K.step);
-        sums[0][threadIdx.x] += double(o.rho[0]);
-        sums[1][threadIdx.x] += double(o.rho[1]);
-        sums[2][threadIdx.x] += double(o.j[0]);
-        sums[3][threadIdx.x] += double(o.j[1]);
-        sums[4][threadIdx.x] += double(o.j[2]);
+        // one LDS add per quantity, no read back (each thread owns its column)
+        atomicAdd(&sums[0][threadIdx.x], double(o.rho[0]));
+        atomicAdd(&sums[1][threadIdx.x], double(o.rho[1]));
+        atomicAdd(&sums[2][threadIdx.x], double(o.j[0]));
+        atomicAdd(&sums[3][threadIdx.x], double(o.j[1]));
+        atomicAdd(&sums[4][threadIdx.x], double(o.j[2]));
       }
       relax_site<C, FORCING, NOISE, MRT>(f, m, K, uint32_t(s));
       store<S, C, NOISE || Storage<S>::deviation, true>(dst, uint32_t(s), f, K.nt);
