@@ -174,7 +174,10 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, d
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
   const float u1 = (float(a) + 0.5f) * 2.3283064365386963e-10f;
   const float u2 = (float(b) + 0.5f) * 2.3283064365386963e-10f;
-  const float r = __fsqrt_rn(-2.0f * __logf(u1));
+  // -2 ln u1 = -2 ln(2) log2(u1) with the hardware base-2 logarithm and
+  // square root: u1 >= 2^-33 and -2 ln u1 >= 2.3e-10 are normal numbers, so
+  // the instructions need none of the library's denormal scaling
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
   // hardware sine/cosine take the angle in turns
   z0 = r * __builtin_amdgcn_cosf(u2);
   z1 = r * __builtin_amdgcn_sinf(u2);
@@ -242,6 +245,8 @@ struct FluidConsts {
   C rho0;  // reference density of deviation storage (0 otherwise)
   uint32_t srkey;  // per-step key of the stochastic rounding of deviations (load_step)
   C lam[4];        // MRT eigenvalues {momentum, bulk, shear, kinetic} (MRT kernels only)
+  C namp[4];       // fluctuation factor per mode group, sqrt(3 kT (1 - (1 + lambda_g)^2))
+                   // (same group order; BGK: lambda_g = -1/tau_A for every group)
 };
 
 // Step index of the launch from the device counter (so that a captured step

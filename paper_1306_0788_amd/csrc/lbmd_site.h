@@ -44,6 +44,40 @@ __host__ __device__ constexpr int mode_b36(int k) {
   return s;
 }
 
+// Mode group of mode k: 0 momentum (1-3), 1 bulk (4), 2 shear (5-9),
+// 3 kinetic (10-18).
+__host__ __device__ constexpr int mode_group(int k) { return k <= 3 ? 0 : (k == 4 ? 1 : (k <= 9 ? 2 : 3)); }
+// Parity of mode k under c -> -c: odd modes change sign between the two
+// velocities of an opposite pair (i, i + 1 for odd i), even modes do not.
+__host__ __device__ constexpr bool mode_odd(int k) {
+  for (int i = 1; i < 19; i += 2)
+    if (mode_e(k, i) != 0) return mode_e(k, i + 1) == -mode_e(k, i);
+  return false;
+}
+__host__ __device__ constexpr bool mode_parity_ok(int k) {
+  for (int i = 1; i < 19; i += 2)
+    if (mode_e(k, i + 1) != (mode_odd(k) ? -mode_e(k, i) : mode_e(k, i))) return false;
+  return !mode_odd(k) || mode_e(k, 0) == 0;
+}
+// square root by Newton's iteration (compile-time tables)
+__host__ __device__ constexpr double ct_sqrt(double x) {
+  double r = x > 1.0 ? x : 1.0;
+  for (int i = 0; i < 80; ++i) r = 0.5 * (r + x / r);
+  return r;
+}
+// per-mode constant of the fluctuation amplitude: 6 / sqrt(36 b_k), i.e.
+// 1 / sqrt(b_k)
+struct NoiseScale {
+  double v[19];
+  constexpr NoiseScale() : v() {
+    for (int k = 1; k < 19; ++k) v[k] = 6.0 / ct_sqrt(double(mode_b36(k)));
+  }
+};
+__device__ constexpr NoiseScale kNoiseScale{};
+static_assert(mode_parity_ok(1) && mode_parity_ok(4) && mode_parity_ok(5) && mode_parity_ok(7) && mode_parity_ok(10) &&
+                  mode_parity_ok(13) && mode_parity_ok(16) && mode_parity_ok(17) && mode_parity_ok(18),
+              "every mode is even or odd under c -> -c");
+
 template <class C>
 struct SiteOut {
   C rho[2];
@@ -242,6 +276,40 @@ __device__ __forceinline__ void coupling_velocity(const Macro<C>& m, C (&uc)[3])
     uc[a] = FORCING == LBMD_FORCE_PAPER ? m.u[0][a] : (m.j[a] + C(0.5) * (m.g[0][a] + m.g[1][a])) * m.inv_rt;
 }
 
+// f_i += w_i sum_k e_ki a_k over the fluctuating modes k = 1..18, written
+// out at compile time: the rest population takes the even modes; each
+// opposite pair (I, I + 1) takes ev + od and ev - od, ev and od the sums of
+// its even and odd modes.
+template <class C, int K, int I>
+__device__ __forceinline__ void modes_at(const C (&a)[19], C& ev, C& od) {
+  if constexpr (K < 19) {
+    constexpr int e = mode_e(K, I);
+    if constexpr (e != 0) {
+      if constexpr (mode_odd(K))
+        od += C(e) * a[K];
+      else
+        ev += C(e) * a[K];
+    }
+    modes_at<C, K + 1, I>(a, ev, od);
+  }
+}
+template <class C>
+__device__ __forceinline__ void modes_to_rest(const C (&a)[19], C& f0) {
+  C ev = 0, od = 0;
+  modes_at<C, 1, 0>(a, ev, od);
+  f0 += weight<C>(0) * ev;
+}
+template <class C, int I>
+__device__ __forceinline__ void modes_to_pairs(const C (&a)[19], C (&f)[19]) {
+  if constexpr (I < 19) {
+    C ev = 0, od = 0;
+    modes_at<C, 1, I>(a, ev, od);
+    f[I] += weight<C>(I) * (ev + od);
+    f[I + 1] += weight<C>(I) * (ev - od);
+    modes_to_pairs<C, I + 2>(a, f);
+  }
+}
+
 // Relaxation of both components (and fluctuations when NOISE).
 template <class C, int FORCING, bool NOISE, bool MRT = false>
 __device__ __forceinline__ void relax_site(C (&f)[2][19], const Macro<C>& m, const FluidConsts<C>& K,
@@ -256,34 +324,31 @@ __device__ __forceinline__ void relax_site(C (&f)[2][19], const Macro<C>& m, con
   if (NOISE) {
     // fluctuations (Appendix, Eq. MODES): 3 shared momentum normals with
     // opposite sign for A and B, 15 per component for the bulk, shear and
-    // kinetic modes; amplitude sqrt(rho (kT/c_s^2) (1-(1+lambda)^2) / b_k)
-    // per mode, mapped back with w_i e_ki
+    // kinetic modes; amplitude of mode k
+    //   sqrt(rho (kT/c_s^2) (1 - (1 + lambda_k)^2) / b_k)
+    //     = sqrt(rho) * namp[group(k)] * (6 / sqrt(36 b_k))
+    // (the group factor from the host, the last one a compile-time
+    // constant), mapped back with w_i e_ki
     C z[36];
 #pragma unroll
     for (int b = 0; b < 9; ++b) normals4<C>(K.seed, K.step, site, b, 0, &z[4 * b]);
-    // per-mode factor 1 - (1 + lambda_k)^2 (BGK: lambda_k = -1/tau)
-    const C om = K.omega[0];
-    const C rA = fmax(m.rho[0], C(0)), rB = fmax(m.rho[1], C(0)), rM = fmax(m.rho[0] * m.rho[1] * m.inv_rt, C(0));
+    const C sA = csqrt(fmax(m.rho[0], C(0))), sB = csqrt(fmax(m.rho[1], C(0)));
+    const C sM = csqrt(fmax(m.rho[0] * m.rho[1] * m.inv_rt, C(0)));
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       C a[19];
 #pragma unroll
       for (int k = 1; k < 19; ++k) {
-        const C l1 = C(1) + (MRT ? mode_lambda<C>(k, K.lam) : -om);
-        const C t = C(3) * K.kT * (C(1) - l1 * l1);
+        const C amp = (MRT ? K.namp[mode_group(k)] : K.namp[0]) * C(kNoiseScale.v[k]);
         if (k < 4)
-          a[k] = (c == 0 ? C(1) : C(-1)) * csqrt(rM * t) * z[k - 1] * C(6) / csqrt(C(mode_b36(k)));
+          a[k] = (c == 0 ? sM : -sM) * amp * z[k - 1];
         else
-          a[k] = csqrt((c == 0 ? rA : rB) * t) * z[3 + 15 * c + (k - 4)] * C(6) / csqrt(C(mode_b36(k)));
+          a[k] = (c == 0 ? sA : sB) * amp * z[3 + 15 * c + (k - 4)];
       }
-#pragma unroll
-      for (int i = 0; i < 19; ++i) {
-        C s = 0;
-#pragma unroll
-        for (int k = 1; k < 19; ++k)
-          if (mode_e(k, i) != 0) s += C(mode_e(k, i)) * a[k];
-        f[c][i] += weight<C>(i) * s;
-      }
+      // back to the populations: the two velocities of an opposite pair share
+      // the even modes' sum and take the odd modes' sum with opposite signs
+      modes_to_rest<C>(a, f[c][0]);
+      modes_to_pairs<C, 1>(a, f[c]);
     }
   }
 }

@@ -3,6 +3,8 @@
 // the deviation encoding), the z-march tile with its LDS density ring and
 // neighbour sums, block reductions, and the per-step constants.
 #pragma once
+#include <algorithm>
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -330,6 +332,12 @@ FluidConsts<arith_t<S>> consts(const lbmd_ctx* h) {
   K.kT = C(h->p.kT);
   K.rho0 = Storage<S>::deviation ? C(h->p.rho0) : C(0);
   for (int q = 0; q < 4; ++q) K.lam[q] = C(h->mrt_lam[q]);
+  for (int q = 0; q < 4; ++q) {
+    // the mode-group part of the fluctuation amplitude (Appendix, Eq. MODES):
+    // each site multiplies it by sqrt(rho_zeta) and a per-mode constant
+    const double l1 = 1.0 + (h->mrt ? h->mrt_lam[q] : -1.0 / h->p.tau[0]);
+    K.namp[q] = C(std::sqrt(std::max(0.0, 3.0 * h->p.kT * (1.0 - l1 * l1))));
+  }
   K.srkey = 0;  // set from the device step counter in the kernel
   K.forcing = h->p.forcing;
   K.noise = h->p.kT > 0.0;
