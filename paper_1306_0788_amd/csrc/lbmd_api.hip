@@ -171,7 +171,10 @@ void free_bonds(lbmd_ctx* h) {
   h->nbonds = 0;
 }
 
-// (re)build the pair-force cell grid for the current cut-off
+// (re)build the cell grid for the current cut-off.  Particles are sorted by
+// cell every step whether or not a pair potential is on: the coupling kernel
+// then takes them in spatial order, so that neighbouring lanes read and
+// update nearby nodes.
 int setup_cells(lbmd_ctx* h) {
   dfree(h->cell_count);
   dfree(h->cell_start);
@@ -192,7 +195,7 @@ int setup_cells(lbmd_ctx* h) {
     h->ncell[a] = n >= 3 ? n : 1;  // fewer than 3 cells would alias neighbours
     h->ncells *= h->ncell[a];
   }
-  if (!(h->pair.wca_on || h->pair.dh_on)) return LBMD_OK;
+  if (h->np == 0) return LBMD_OK;
   HIPCHECK(h, dalloc(&h->cell_count, h->ncells + 1));
   HIPCHECK(h, dalloc(&h->cell_start, h->ncells + 1));
   HIPCHECK(h, dalloc(&h->scan_block, (h->ncells + 1 + 1023) / 1024 + 1));
@@ -618,7 +621,7 @@ int lbmd_set_particles(lbmd_handle h, int64_t n, const double* pos, const double
   const bool regrid = n != h->np;
   h->np = n;
   h->red_part_used = 0;
-  if (regrid && (h->pair.wca_on || h->pair.dh_on))
+  if (regrid)
     if (int rc = setup_cells(h)) return rc;
   if (n > 0) {
     if (int rc = ensure_coupling_buffers(h)) return rc;

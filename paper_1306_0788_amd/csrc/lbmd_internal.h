@@ -222,7 +222,7 @@ struct PartArgs {
   PairParams pp;
   int ncell[3];
   double rcut;  // largest non-bonded cut-off (cells farther than it are skipped)
-  int use_cells;
+  int use_cells;  // particles sorted by cell (perm, xs) this step
   int build_list;  // append touched nodes to the compact list (fused organisation)
   int mark_in_couple;  // the coupling kernel marks the touched nodes (push organisation)
 };
@@ -302,11 +302,16 @@ struct MomentView {
     const int bx = x >> 6, xl = x & 63;
     const int tw = nx - (bx << 6) < 64 ? nx - (bx << 6) : 64;
     const uint32_t off = (uint32_t(z) * uint32_t(ny) + uint32_t(y)) * uint32_t(sizeof(C));
-    if (xl == 0)
-      v += rsrc_load<C>(H, off + uint32_t(2 * (bx == 0 ? tiles_x - 1 : bx - 1) + 1) * sideH, uint32_t(q) * qH);
-    if (xl == tw - 1) v += rsrc_load<C>(H, off + uint32_t(2 * (bx == tiles_x - 1 ? 0 : bx + 1)) * sideH, uint32_t(q) * qH);
-    return v;
+    // the side-buffer terms at the first and last column of a tile, without
+    // branches: elsewhere the offset lies beyond the side buffer's record
+    // count, where a raw buffer load returns zero and touches no memory
+    // (adding that zero leaves v unchanged)
+    const uint32_t ol = xl == 0 ? off + uint32_t(2 * (bx == 0 ? tiles_x - 1 : bx - 1) + 1) * sideH : kBeyond;
+    const uint32_t orr = xl == tw - 1 ? off + uint32_t(2 * (bx == tiles_x - 1 ? 0 : bx + 1)) * sideH : kBeyond;
+    v += rsrc_load<C>(H, ol, uint32_t(q) * qH);
+    return v + rsrc_load<C>(H, orr, uint32_t(q) * qH);
   }
+  static constexpr uint32_t kBeyond = 0xFFFFFF00u;  // above any side buffer (< 4 GiB)
 };
 // the view of step `step` into R[3][5][N] and H[2][tiles_x][2][5][nz][ny]
 template <class C>

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
   const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
   double Fp[3] = {0, 0, 0};
   const double L[3] = {double(A.nx), double(A.ny), double(A.nz)};
-  if (A.use_cells) {
+  if (A.use_cells && (A.pp.wca_on || A.pp.dh_on)) {
     const int c = cell_of[p];
     const int cc[3] = {c % A.ncell[0], (c / A.ncell[0]) % A.ncell[1], c / (A.ncell[0] * A.ncell[1])};
     int lo[3], hi[3];
@@ -631,7 +631,7 @@ static PartArgs args(const lbmd_ctx* h) {
   A.pp = h->pair;
   for (int a = 0; a < 3; ++a) A.ncell[a] = h->ncell[a];
   A.rcut = h->rcut;
-  A.use_cells = (h->pair.wca_on || h->pair.dh_on) ? 1 : 0;
+  A.use_cells = h->np > 0 && h->cell_start ? 1 : 0;  // particles sorted by cell (always, when there are any)
   A.build_list = organisation_of(h) == LBMD_KERNEL_FUSED ? 1 : 0;
   A.mark_in_couple = organisation_of(h) == LBMD_KERNEL_PUSH ? 1 : 0;
   return A;
