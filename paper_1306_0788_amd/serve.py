@@ -132,11 +132,32 @@ def _failed_step(sim):
 
 
 def summarize(jobs, rec):
+    """Latency percentiles over the completed jobs, throughput over all
+    lattice-site updates done, and where the failed jobs lie in G_AB (the
+    failure is the model's: a density reaches zero)."""
     done = [r for r in rec if not r["failed"]]
     lat = np.array([r["done"] - r["arrival"] for r in done])
     sites = sum(int(np.prod(jobs[i]["shape"])) * rec[i]["steps"] for i in range(len(jobs)))
     span = max(r["done"] for r in rec) - min(r["arrival"] for r in rec)
-    return {"jobs": len(jobs), "completed": len(done), "failed": len(rec) - len(done),
-            "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
-            "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
-            "aggregate_MLUPS": sites / span / 1e6, "makespan_s": span}
+    out = {"jobs": len(jobs), "completed": len(done), "failed": len(rec) - len(done),
+           "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+           "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+           "aggregate_MLUPS": sites / span / 1e6, "makespan_s": span}
+    G = np.array([j["G"] for j in jobs])
+    failed = np.array([r["failed"] for r in rec])
+    if failed.any():
+        edges = np.round(np.arange(1.6, 2.21, 0.1), 2)
+        bins = []
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            sel = (G >= lo) & (G < hi + (1e-9 if hi >= 2.2 else 0.0))
+            bins.append({"G": [float(lo), float(hi)], "jobs": int(sel.sum()), "failed": int((failed & sel).sum())})
+        out["failures"] = {
+            "cause": "a density reached zero, the model's own failure at these inputs: small droplets "
+                     "compressed above their coexistence density at larger G_AB, and dense solvated "
+                     "particles at any G_AB (the FP64 CPU oracle fails the same jobs; "
+                     "tests/test_oracle_serving_jobs.py)",
+            "G_min_failed": float(G[failed].min()),
+            "G_max_completed": float(G[~failed].max()) if (~failed).any() else None,
+            "median_failed_step": float(np.median([r["steps"] for r in np.array(rec)[failed]])),
+            "by_G": bins}
+    return out
