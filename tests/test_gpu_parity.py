@@ -110,6 +110,17 @@ def test_chains_fene_wca_debye_hueckel(precision, tol, kernel):
     compare(c, g, o, tol, tol, "chains")
 
 
+@pytest.mark.parametrize("shape,chains", [((30, 22, 26), (12, 20)), ((17, 40, 21), (10, 25))])
+def test_pair_cells_dense_chains(shape, chains):
+    """Dense bead chains with the Debye-Hueckel cut-off 3 in ragged boxes
+    (cell rows whose x-runs wrap around the box); forces against the
+    all-pairs oracle."""
+    c = Case(shape, FP64, PAPER, TWOPASS, G=1.5, gamma=1.0, seed=5, chains=chains, kappa=((0.1, 0.0),),
+             mass=(2000.0,), charge=(1.0,), wca=(1.0, 1.0), fene=(30.0, 1.5), dh=(1.3, 3.0, 0.8))
+    g, o = run_pair(c, 3)
+    compare(c, g, o, 1e-11, 1e-11, "pair cells, dense chains")
+
+
 @pytest.mark.parametrize("kernel", [FUSED, TWOPASS, PUSH])
 def test_particles_on_nodes_edges_and_shared_cells(kernel):
     L = 12
