@@ -26,7 +26,14 @@
 namespace lbmd {
 
 
-__device__ __forceinline__ double min_image(double d, double L) { return d - L * floor(d / L + 0.5); }
+// Minimum image of a difference d of two positions in [0, L) (so |d| < L):
+// a compare and a subtraction instead of an FP64 division.  It differs from
+// d - L floor(d / L + 1/2) only at |d| = L/2 exactly, beyond every cut-off
+// (the pair and bond ranges are checked to stay below half the box).
+__device__ __forceinline__ double min_image(double d, double L) {
+  const double h = 0.5 * L;
+  return d > h ? d - L : (d < -h ? d + L : d);
+}
 
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
@@ -212,9 +219,10 @@ __global__ void k_scatter(const int32_t* __restrict__ cell_of, const int32_t* __
   xs[4 * k + 3] = T.charge[type[p]];
 }
 
-__device__ __forceinline__ void add_radial(double fr, const double (&d)[3], double r, double (&Fp)[3]) {
-  // fr = -dU/dr (positive = repulsive); d points from p to the partner
-  for (int a = 0; a < 3; ++a) Fp[a] -= fr * d[a] / r;
+__device__ __forceinline__ void add_radial(double fr_over_r, const double (&d)[3], double (&Fp)[3]) {
+  // fr = -dU/dr (positive = repulsive), passed divided by r; d points from p
+  // to the partner
+  for (int a = 0; a < 3; ++a) Fp[a] -= fr_over_r * d[a];
 }
 
 // Conservative forces (pair potentials from the cell list, FENE bonds) at
@@ -303,15 +311,22 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
             double d[3];
             for (int a = 0; a < 3; ++a) d[a] = min_image(xs[4 * jj + a] - xp[a], L[a]);
             const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const bool wca = A.pp.wca_on && r2 < A.pp.wca_rc2;
             const double r = sqrt(r2);
-            if (A.pp.wca_on && r2 < A.pp.wca_rc2) {
-              const double s2 = A.pp.wca_sigma * A.pp.wca_sigma / r2;
-              const double s6 = s2 * s2 * s2;
-              add_radial(24.0 * A.pp.wca_eps * (2.0 * s6 * s6 - s6) / r, d, r, Fp);
-            }
-            if (A.pp.dh_on && r < A.pp.dh_rc) {
-              const double qq = qp * xs[4 * jj + 3];
-              add_radial(qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) / r2, d, r, Fp);
+            const bool dh = A.pp.dh_on && r < A.pp.dh_rc;
+            if (wca || dh) {
+              const double inv_r2 = 1.0 / r2;
+              double fr_over_r = 0.0;  // -dU/dr / r
+              if (wca) {
+                const double s2 = A.pp.wca_sigma * A.pp.wca_sigma * inv_r2;
+                const double s6 = s2 * s2 * s2;
+                fr_over_r += 24.0 * A.pp.wca_eps * (2.0 * s6 * s6 - s6) * inv_r2;
+              }
+              if (dh) {
+                const double qq = qp * xs[4 * jj + 3];
+                fr_over_r += qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) * inv_r2 / r;
+              }
+              add_radial(fr_over_r, d, Fp);
             }
           }
         }
@@ -324,8 +339,9 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
       for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
       const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       const double qr = r / A.pp.fene_R0;
-      const double fr = qr < 1.0 ? -A.pp.fene_k * r / (1.0 - qr * qr) : __builtin_nan("");
-      add_radial(fr, d, r, Fp);
+      // -dU/dr / r of FENE: -k / (1 - (r/R0)^2)
+      const double fr_over_r = qr < 1.0 ? -A.pp.fene_k / (1.0 - qr * qr) : __builtin_nan("");
+      add_radial(fr_over_r, d, Fp);
     }
   }
   for (int a = 0; a < 3; ++a) Fcons[3 * p + a] = Fp[a];
