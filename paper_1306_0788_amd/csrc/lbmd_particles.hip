@@ -229,10 +229,22 @@ __device__ __forceinline__ void add_radial(double fr_over_r, const double (&d)[3
 // the new positions; independent of the fluid, so it runs on a second stream
 // while the density pass streams the populations.
 // sum over the 8 lanes of an aligned lane group, identical on every lane
-// (each butterfly level adds the same two values)
+// (each butterfly level adds the same two values).  The partners come from
+// DPP lane moves, no LDS round trip: quad permutations for lane ^ 1 and
+// lane ^ 2, then the half-row mirror (lane i of the group with lane 7 - i),
+// which after the first two levels holds the other quad's sum, the same
+// value lane ^ 4 holds.  All 8 lanes of a group take part together.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b)), CTRL, 0xf, 0xf, false));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), CTRL, 0xf, 0xf, false));
+  return __builtin_bit_cast(double, uint64_t(lo) | (uint64_t(hi) << 32));
+}
 __device__ __forceinline__ double group8_sum(double v) {
-#pragma unroll
-  for (int o = 1; o < 8; o <<= 1) v += __shfl_xor(v, o, 64);
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp_move<0x141>(v);  // row_half_mirror: lane 7 - i within 8
   return v;
 }
 
