@@ -281,7 +281,7 @@ def _emulsion(args):
     return workloads.emulsion_job(*args)
 
 
-def serving(njobs, rate, seed, max_jobs, mem_gib, one_by_one, jobs):
+def serving(njobs, rate, seed, max_jobs, mem_gib, one_by_one, jobs, single_batch=False):
     """The serving workload: a Poisson stream of emulsion jobs served with
     continuous batching (and, if asked, one job at a time)."""
     from paper_1306_0788_amd import serve, workloads
@@ -295,10 +295,17 @@ def serving(njobs, rate, seed, max_jobs, mem_gib, one_by_one, jobs):
         if count[0] % 64 == 0:
             print("serve: %d jobs finished (%s)" % (count[0], msg), file=sys.stderr, flush=True)
 
-    rb = serve.serve_batched(jobs, arrivals, max_jobs=max_jobs, mem_budget=mem_gib << 30, chunk=10, log=progress)
+    rb = serve.serve_batched_classes(jobs, arrivals, bounds=(64 ** 3,), max_jobs=max_jobs,
+                                     mem_budget=mem_gib << 30, chunk=10, log=progress)
     out = {"jobs": njobs, "arrival_rate_per_s": rate, "steps_per_job": jobs[0]["steps"],
            "lattice_sites_mean": float(np.mean([np.prod(j["shape"]) for j in jobs])),
-           "slots": max_jobs, "memory_budget_GiB": mem_gib, "batched": serve.summarize(jobs, rb)}
+           "slots": max_jobs, "memory_budget_GiB": mem_gib,
+           "batched": dict(serve.summarize(jobs, rb), size_classes="<= 64^3 sites, larger: one batch each")}
+    if single_batch:
+        print("serve: the same stream in one batch for all sizes", file=sys.stderr, flush=True)
+        count[0] = 0
+        r1 = serve.serve_batched(jobs, arrivals, max_jobs=max_jobs, mem_budget=mem_gib << 30, chunk=10, log=progress)
+        out["batched_one_class"] = serve.summarize(jobs, r1)
     if one_by_one:
         print("serve: the same stream one job at a time", file=sys.stderr, flush=True)
         count[0] = 0
@@ -399,6 +406,8 @@ def main():
     ap.add_argument("--serve-mem-gib", type=int, default=64)
     ap.add_argument("--serve-one-by-one", action="store_true",
                     help="also serve the stream one job at a time for comparison")
+    ap.add_argument("--serve-one-batch", action="store_true",
+                    help="also serve the stream with one batch for all sizes (no size classes)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving workload")
     ap.add_argument("--accuracy", type=int, default=None, metavar="STEPS",
                     help="instead of timing: error of every storage form against the FP64 step after STEPS steps")
@@ -439,7 +448,8 @@ def main():
     if args.serve_only:
         torch.cuda.set_device(0)
         print(json.dumps({"served": serving(args.serve_jobs, args.serve_rate, 5, args.serve_slots,
-                                            args.serve_mem_gib, args.serve_one_by_one, jobs)}), flush=True)
+                                            args.serve_mem_gib, args.serve_one_by_one, jobs,
+                                            args.serve_one_batch)}), flush=True)
         return
     torch.cuda.set_device(0)
     # a dedicated stream (the current one may be the null stream, handle 0,
@@ -517,7 +527,7 @@ def main():
                        "particle_updates_per_s": round(rx["npart"] * kx / (rx["ms"] * 1e-3), 1)}
     if jobs is not None:
         line["served"] = serving(args.serve_jobs, args.serve_rate, 5, args.serve_slots, args.serve_mem_gib,
-                                 args.serve_one_by_one, jobs)
+                                 args.serve_one_by_one, jobs, args.serve_one_batch)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.workload)

@@ -13,6 +13,7 @@ Time-to-completion of a job = completion time - arrival time (queueing,
 set-up, stepping).  Aggregate MLUPS = lattice site updates of all completed
 steps / (last completion - first arrival).
 """
+import threading
 import time
 from collections import deque
 
@@ -95,6 +96,106 @@ def serve_batched(jobs, arrivals, max_jobs=32, mem_budget=64 << 30, chunk=10, lo
                 time.sleep(max(0.0, min(0.01, arrivals[pending[0]] - (time.perf_counter() - t0))))
     finally:
         batch.close()
+    return rec
+
+
+def serve_batched_classes(jobs, arrivals, bounds=(64 ** 3,), max_jobs=32, mem_budget=64 << 30, chunk=10,
+                          log=None):
+    """Continuous batching by size class: the jobs are split by lattice size
+    (class c takes the jobs with bounds[c-1] < sites <= bounds[c], the last
+    class the rest), and each class is served by its own batch on its own
+    stream, driven by its own host thread (the library calls release the
+    interpreter lock while they wait).  A small job then advances at the pace
+    of the small jobs' batch step instead of that of the largest box resident.
+    Admission order, the memory budget and the records are shared; slots are
+    split evenly between the classes.  Returns the records of serve_batched."""
+    n = len(jobs)
+    ncls = len(bounds) + 1
+
+    def cls(i):
+        sites = int(np.prod(jobs[i]["shape"]))
+        for c, b in enumerate(bounds):
+            if sites <= b:
+                return c
+        return ncls - 1
+
+    for i in range(n):
+        if footprint(jobs[i]) > mem_budget:
+            raise RuntimeError("job %d does not fit the memory budget" % i)
+    lbmd.load()  # the library is loaded once, before the workers start
+    rec = [dict(arrival=float(arrivals[i]), admitted=None, done=None, steps=0, failed=False) for i in range(n)]
+    pending = deque(range(n))
+    queues = [deque() for _ in range(ncls)]
+    slots = [max(1, max_jobs // ncls)] * ncls
+    shared = {"used": 0, "finished": 0}
+    lock = threading.Lock()
+    errors = []
+    t0 = time.perf_counter()
+
+    def arrived():
+        now = time.perf_counter() - t0
+        while pending and arrivals[pending[0]] <= now:
+            i = pending.popleft()
+            queues[cls(i)].append(i)
+
+    def worker(c):
+        batch = lbmd.Batch(max_jobs=slots[c], noise=False)
+        active = {}
+        try:
+            while True:
+                with lock:
+                    arrived()
+                    if shared["finished"] == n:
+                        break
+                if active:
+                    batch.step(chunk)
+                take = []
+                with lock:
+                    while (queues[c] and len(active) + len(take) < slots[c] and
+                           shared["used"] + footprint(jobs[queues[c][0]]) <= mem_budget):
+                        i = queues[c].popleft()
+                        take.append(i)
+                        shared["used"] += footprint(jobs[i])
+                new = [(i, make_sim(jobs[i], kernel=lbmd.KERNEL_FUSED)) for i in take]
+                if active:
+                    steps, state = batch.poll()
+                    t = time.perf_counter() - t0
+                    for slot in list(active):
+                        if state[slot] in (lbmd.DONE, lbmd.FAILED):
+                            i, sim, b = active.pop(slot)
+                            batch.detach(slot)
+                            rec[i]["done"] = t
+                            rec[i]["steps"] = int(steps[slot])
+                            rec[i]["failed"] = state[slot] == lbmd.FAILED
+                            sim.close()
+                            with lock:
+                                shared["used"] -= b
+                                shared["finished"] += 1
+                            if log:
+                                log("job %d (%s) %s at %.3f s" % (i, jobs[i]["shape"][0],
+                                                                 "failed" if rec[i]["failed"] else "done", t))
+                for i, sim in new:
+                    slot = batch.attach(sim, jobs[i]["steps"])
+                    active[slot] = (i, sim, footprint(jobs[i]))
+                    rec[i]["admitted"] = time.perf_counter() - t0
+                if not active:
+                    with lock:
+                        nxt = arrivals[pending[0]] - (time.perf_counter() - t0) if pending else 0.002
+                    time.sleep(max(0.0005, min(0.005, nxt)))
+        except Exception as e:  # surfaced by the caller after the join
+            errors.append(e)
+            with lock:
+                shared["finished"] = n  # let the other threads end
+        finally:
+            batch.close()
+
+    threads = [threading.Thread(target=worker, args=(c,)) for c in range(ncls)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    if errors:
+        raise errors[0]
     return rec
 
 

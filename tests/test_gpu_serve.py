@@ -179,3 +179,18 @@ def test_serving_loop_completes_every_job():
         assert not r["failed"] and r["steps"] == j["steps"] and r["done"] >= r["arrival"]
     s = serve.summarize(jobs, rec)
     assert s["completed"] == len(jobs) and s["p99_s"] >= s["p50_s"] > 0
+
+
+def test_size_class_serving_completes_every_job():
+    jobs = []
+    for i, L in enumerate((20, 40, 36, 24, 32, 16, 44)):
+        j = job((L, L, L), 1.5, 30 + i, npart=30 + 10 * i)
+        j["steps"] = 40 + 5 * i
+        jobs.append(j)
+    arrivals = np.array([0.0, 0.01, 0.02, 0.05, 0.06, 0.2, 0.21])
+    print("size-class serving loop", flush=True)
+    rec = serve.serve_batched_classes(jobs, arrivals, bounds=(28 ** 3,), max_jobs=4, mem_budget=1 << 30, chunk=8)
+    for j, r in zip(jobs, rec):
+        assert not r["failed"] and r["steps"] == j["steps"] and r["done"] >= r["admitted"] >= r["arrival"]
+    s = serve.summarize(jobs, rec)
+    assert s["completed"] == len(jobs) and s["p99_s"] >= s["p50_s"] > 0
