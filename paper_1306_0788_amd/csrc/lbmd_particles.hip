@@ -21,6 +21,8 @@
 // All particle quantities are float64.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbmd_internal.h"
 
 namespace lbmd {
@@ -248,14 +250,42 @@ __device__ __forceinline__ double group8_sum(double v) {
   return v;
 }
 
-// Pair and bond forces, one thread per particle in cell order (neighbouring
-// threads share cells).  The cells of one x row are consecutive in the
-// sorted order, so each (y, z) row of neighbour cells is one contiguous run
-// of xs; rows and columns of cells whose nearest face lies beyond the
-// cut-off from the particle are skipped (the face distance is measured in
-// FP64 with a margin, so no pair inside the cut-off is lost).  The force on
-// a particle is the sum of its pair terms, each evaluated exactly as before.
+// Pair and bond forces, eight lanes per particle in cell order.  The cells
+// of one x row are consecutive in the sorted order, so each (y, z) row of
+// neighbour cells is one contiguous run of xs (two where the row wraps in
+// x); rows and columns of cells whose nearest face lies beyond the cut-off
+// from the particle are skipped (the face distance is measured in FP64 with
+// a margin, so no pair inside the cut-off is lost).  The eight lanes look
+// up all run bounds together (one round trip to memory) into an LDS table,
+// then take consecutive candidates of each run together (one 256-byte piece
+// of xs per round) in one rolled loop over the runs, which keeps the kernel
+// at 94 registers.  Each pair term is evaluated as in a one-lane loop; the
+// lanes' partial sums are added by the 8-lane butterfly.
 constexpr int PAIRS_BLOCK = 256;
+constexpr int PAIRS_PER_BLOCK = PAIRS_BLOCK / 8;
+
+// -dU/dr / r of the pair potentials at squared distance r2 (0 beyond both
+// cut-offs); qq = q_p q_j
+__device__ __forceinline__ double pair_fr_over_r(const PartArgs& A, double r2, double qq, double dh_pre2) {
+  const bool wca = A.pp.wca_on && r2 < A.pp.wca_rc2;
+  // the square root only for candidates that can lie inside the screened
+  // Coulomb cut-off (dh_pre2 is rc^2 rounded up); the cut-off test itself is
+  // on r, as in the definition
+  if (!(wca || (A.pp.dh_on && r2 < dh_pre2))) return 0.0;
+  const double r = sqrt(r2);
+  const bool dh = A.pp.dh_on && r < A.pp.dh_rc;
+  if (!(wca || dh)) return 0.0;
+  const double inv_r = 1.0 / r, inv_r2 = inv_r * inv_r;
+  double fr_over_r = 0.0;
+  if (wca) {
+    const double s2 = A.pp.wca_sigma * A.pp.wca_sigma * inv_r2;
+    const double s6 = s2 * s2 * s2;
+    fr_over_r += 24.0 * A.pp.wca_eps * (2.0 * s6 * s6 - s6) * inv_r2;
+  }
+  if (dh) fr_over_r += qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) * inv_r2 * inv_r;
+  return fr_over_r;
+}
+
 __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double* __restrict__ x,
                                                        const int32_t* __restrict__ type,
                                                        const int32_t* __restrict__ cell_start,
@@ -264,15 +294,20 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
                                                        const double* __restrict__ xs,
                                                        const int32_t* __restrict__ bstart,
                                                        const int32_t* __restrict__ bnbr, double* __restrict__ Fcons) {
-  const int64_t k = int64_t(blockIdx.x) * PAIRS_BLOCK + threadIdx.x;  // sorted position
-  if (k >= A.np) return;
-  const int64_t p = A.use_cells ? int64_t(perm[k]) : k;
-  const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
+  // per group: the [begin, end) of the up to 18 runs of xs it scans
+  __shared__ int2 runs[PAIRS_PER_BLOCK][18];
+  const int grp = int(threadIdx.x >> 3), lane = int(threadIdx.x & 7);
+  // sorted position of the group's particle
+  const int64_t k = int64_t(blockIdx.x) * PAIRS_PER_BLOCK + grp;
+  const bool live = k < A.np;
+  const int64_t p = !live ? 0 : (A.use_cells ? int64_t(perm[k]) : k);
+  const double xp[3] = {live ? x[3 * p] : 0.0, live ? x[3 * p + 1] : 0.0, live ? x[3 * p + 2] : 0.0};
   double Fp[3] = {0, 0, 0};
   const double L[3] = {double(A.nx), double(A.ny), double(A.nz)};
-  if (A.use_cells && (A.pp.wca_on || A.pp.dh_on)) {
-    const int c = cell_of[p];
-    const int cc[3] = {c % A.ncell[0], (c / A.ncell[0]) % A.ncell[1], c / (A.ncell[0] * A.ncell[1])};
+  if (A.use_cells && (A.pp.wca_on || A.pp.dh_on)) {  // the same for the whole block
+    const int c = live ? cell_of[p] : 0;
+    const int nc0 = A.ncell[0], nc1 = A.ncell[1], nc2 = A.ncell[2];
+    const int cc[3] = {c % nc0, (c / nc0) % nc1, c / (nc0 * nc1)};
     int lo[3], hi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -287,65 +322,70 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
       lo[a] = off < A.rcut + margin ? -1 : 0;
       hi[a] = edge - off < A.rcut + margin ? 1 : 0;
     }
-    const double qp = A.T.charge[type[p]];
-    for (int dz = lo[2]; dz <= hi[2]; ++dz)
-      for (int dy = lo[1]; dy <= hi[1]; ++dy) {
-        const int zc = wrapi(cc[2] + dz, A.ncell[2]), yc = wrapi(cc[1] + dy, A.ncell[1]);
-        const int row = (zc * A.ncell[1] + yc) * A.ncell[0];
-        // the x run of cells cc[0] + lo .. cc[0] + hi, split where it wraps
-        int x0 = cc[0] + lo[0], x1 = cc[0] + hi[0];
-        int runs[2][2], nr = 0;
-        if (A.ncell[0] < 3) {
-          runs[0][0] = row;
-          runs[0][1] = row + A.ncell[0];
-          nr = 1;
-        } else if (x0 < 0) {
-          runs[0][0] = row + A.ncell[0] - 1;
-          runs[0][1] = row + A.ncell[0];
-          runs[1][0] = row;
-          runs[1][1] = row + x1 + 1;
-          nr = 2;
-        } else if (x1 >= A.ncell[0]) {
-          runs[0][0] = row + x0;
-          runs[0][1] = row + A.ncell[0];
-          runs[1][0] = row;
-          runs[1][1] = row + 1;
-          nr = 2;
-        } else {
-          runs[0][0] = row + x0;
-          runs[0][1] = row + x1 + 1;
-          nr = 1;
-        }
-        for (int rr = 0; rr < nr; ++rr) {
-          const int jb = cell_start[runs[rr][0]], je = cell_start[runs[rr][1]];
-          for (int jj = jb; jj < je; ++jj) {
-            if (jj == k) continue;
-            double d[3];
-            for (int a = 0; a < 3; ++a) d[a] = min_image(xs[4 * jj + a] - xp[a], L[a]);
-            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            const bool wca = A.pp.wca_on && r2 < A.pp.wca_rc2;
-            const double r = sqrt(r2);
-            const bool dh = A.pp.dh_on && r < A.pp.dh_rc;
-            if (wca || dh) {
-              const double inv_r2 = 1.0 / r2;
-              double fr_over_r = 0.0;  // -dU/dr / r
-              if (wca) {
-                const double s2 = A.pp.wca_sigma * A.pp.wca_sigma * inv_r2;
-                const double s6 = s2 * s2 * s2;
-                fr_over_r += 24.0 * A.pp.wca_eps * (2.0 * s6 * s6 - s6) * inv_r2;
-              }
-              if (dh) {
-                const double qq = qp * xs[4 * jj + 3];
-                fr_over_r += qq * A.pp.dh_lB * exp(-A.pp.dh_kappa * r) * (1.0 + A.pp.dh_kappa * r) * inv_r2 / r;
-              }
-              add_radial(fr_over_r, d, Fp);
-            }
-          }
+    // the x run of cells cc[0] + lo .. cc[0] + hi as up to two runs of cell
+    // indices within a row, split where it wraps
+    int ra0, ra1, rb0 = 0, rb1 = 0;
+    const int x0 = cc[0] + lo[0], x1 = cc[0] + hi[0];
+    if (nc0 < 3) {
+      ra0 = 0;
+      ra1 = nc0;
+    } else if (x0 < 0) {
+      ra0 = nc0 - 1;
+      ra1 = nc0;
+      rb0 = 0;
+      rb1 = x1 + 1;
+    } else if (x1 >= nc0) {
+      ra0 = x0;
+      ra1 = nc0;
+      rb0 = 0;
+      rb1 = 1;
+    } else {
+      ra0 = x0;
+      ra1 = x1 + 1;
+    }
+    // the lanes look up the rows' run bounds together (lane l: rows l and
+    // l + 8), one round trip to memory
+    for (int i = lane; i < 9; i += 8) {
+      const int dz = i / 3 - 1, dy = i % 3 - 1;
+      const bool on = live && dz >= lo[2] && dz <= hi[2] && dy >= lo[1] && dy <= hi[1];
+      const int row = (wrapi(cc[2] + dz, nc2) * nc1 + wrapi(cc[1] + dy, nc1)) * nc0;
+      runs[grp][2 * i] = on ? make_int2(cell_start[row + ra0], cell_start[row + ra1]) : make_int2(0, 0);
+      runs[grp][2 * i + 1] =
+          on && rb1 > rb0 ? make_int2(cell_start[row + rb0], cell_start[row + rb1]) : make_int2(0, 0);
+    }
+    __syncthreads();
+    const double qp = live ? A.T.charge[type[p]] : 0.0;
+    const double dh_pre2 = A.pp.dh_rc * A.pp.dh_rc * (1.0 + 1e-12);
+    // where no neighbour cell wraps around the box and the box holds at
+    // least 5 cells per axis, every separation is below two cell edges, less
+    // than half the box, so the minimum image is the plain difference
+    bool inner = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inner = inner && A.ncell[a] >= 5 && cc[a] + lo[a] >= 0 && cc[a] + hi[a] < A.ncell[a];
+    auto scan = [&](auto wrap) {
+#pragma unroll 1
+      for (int r = 0; r < 18; ++r) {
+        const int2 rr = runs[grp][r];
+        for (int jj = rr.x + lane; jj < rr.y; jj += 8) {
+          if (jj == k) continue;
+          const double4 q = *reinterpret_cast<const double4*>(xs + 4 * int64_t(jj));
+          double d[3] = {q.x - xp[0], q.y - xp[1], q.z - xp[2]};
+          if (decltype(wrap)::value)
+            for (int a = 0; a < 3; ++a) d[a] = min_image(d[a], L[a]);
+          const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          const double fr_over_r = pair_fr_over_r(A, r2, qp * q.w, dh_pre2);
+          if (fr_over_r != 0.0) add_radial(fr_over_r, d, Fp);
         }
       }
+    };
+    if (inner)
+      scan(std::false_type{});
+    else
+      scan(std::true_type{});
   }
+  if (!live) return;  // whole groups, after the block's barrier
   if (A.pp.fene_on && bstart) {
-    for (int jj = bstart[p]; jj < bstart[p + 1]; ++jj) {
+    for (int jj = bstart[p] + lane; jj < bstart[p + 1]; jj += 8) {
       const int q = bnbr[jj];
       double d[3];
       for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
@@ -356,7 +396,8 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
       add_radial(fr_over_r, d, Fp);
     }
   }
-  for (int a = 0; a < 3; ++a) Fcons[3 * p + a] = Fp[a];
+  const double F0 = group8_sum(Fp[0]), F1 = group8_sum(Fp[1]), F2 = group8_sum(Fp[2]);
+  if (lane < 3) Fcons[3 * p + lane] = lane == 0 ? F0 : (lane == 1 ? F1 : F2);
 }
 
 // Coupling force: trilinear interpolation of u_c and the lattice density
@@ -723,7 +764,7 @@ hipError_t particles_pairs(lbmd_ctx* h) {
   if (!has_conservative(h)) return hipSuccess;
   PartArgs A = args(h);
   if (hipError_t e = hipStreamWaitEvent(h->side, h->ev_sorted, 0)) return e;
-  const int64_t nb = (h->np + PAIRS_BLOCK - 1) / PAIRS_BLOCK;
+  const int64_t nb = (h->np + PAIRS_PER_BLOCK - 1) / PAIRS_PER_BLOCK;
   hipLaunchKernelGGL(k_pairs, dim3(nb), dim3(PAIRS_BLOCK), 0, h->side, A, h->x, h->type, h->cell_start, h->cell_perm,
                      h->cell_of, h->xs, h->bond_start, h->bond_nbr, h->Fcons);
   if (hipError_t e = hipGetLastError()) return e;
