@@ -65,7 +65,7 @@ int upload(lbmd_batch_s* b) {
       }
     if (t >= BATCH_FLUID_GRID) break;
   }
-  int64_t tiles = 0, pblk = 0, fix = 0;
+  int64_t tiles = 0, pblk = 0, fix = 0, cmp = 0;
   for (int s = 0; s < b->max_jobs; ++s) {
     lbmd_ctx* h = b->job[s];
     if (!h) continue;
@@ -77,15 +77,18 @@ int upload(lbmd_batch_s* b) {
     J.tile_begin = tiles;
     J.pblk_begin = pblk;
     J.fix_begin = fix;
+    J.cmp_begin = cmp;
     tiles += J.nblk;
     pblk += J.npblk;
     fix += J.nfixblk;
+    cmp += J.ncmpblk;
     b->row_slot.push_back(s);
   }
   b->hdr_host->njobs = int32_t(b->row_slot.size());
   b->hdr_host->ntiles = tiles;
   b->hdr_host->npblk = pblk;
   b->hdr_host->nfixblk = fix;
+  b->hdr_host->ncmpblk = cmp;
   if (!b->row_slot.empty())
     BHIP(b, hipMemcpyAsync(b->tab, b->tab_host, b->row_slot.size() * sizeof(BatchJob), hipMemcpyHostToDevice,
                            b->stream));

@@ -223,7 +223,7 @@ struct PartArgs {
   int ncell[3];
   double rcut;  // largest non-bonded cut-off (cells farther than it are skipped)
   int use_cells;  // particles sorted by cell (perm, xs) this step
-  int build_list;  // append touched nodes to the compact list (fused organisation)
+  int build_list;  // compact the touched nodes into a list after the marks (fused organisation)
   int mark_in_couple;  // the coupling kernel marks the touched nodes (push organisation)
 };
 
@@ -364,12 +364,14 @@ struct BatchJob {
   double* Fc;
   int32_t* type;
   int64_t npblk, nfixblk;                     // particle and node-list blocks
+  int64_t words, ncmpblk;                     // mask words, their compaction blocks
   int64_t tile_begin, pblk_begin, fix_begin;  // offsets in the flattened work
+  int64_t cmp_begin;
 };
 struct BatchHeader {
   int32_t njobs;
   int32_t pad;
-  int64_t ntiles, npblk, nfixblk;
+  int64_t ntiles, npblk, nfixblk, ncmpblk;
 };
 constexpr int BATCH_TY = 4;
 constexpr int BATCH_FLUID_GRID = 2048;  // blocks of the fused batch kernel

@@ -78,7 +78,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ void begin_block(const PartArgs& A, double* __restrict__ x, double* __restrict__ v,
                                             const double* __restrict__ F, const double* __restrict__ Fc,
                                             const int32_t* __restrict__ type, uint32_t* __restrict__ mask,
-                                            int32_t* __restrict__ list, int32_t* __restrict__ nlist,
                                             int32_t* __restrict__ cell_count, int32_t* __restrict__ cell_of,
                                             int32_t* __restrict__ rank_of, double* __restrict__ red, int64_t blk) {
   __shared__ double part[4][3];
@@ -109,37 +108,11 @@ __device__ __forceinline__ void begin_block(const PartArgs& A, double* __restric
     }
   }
   // mark the 8 nodes (push organisation: the coupling kernel does, in cell
-  // order, where neighbouring particles' nodes share cache lines); with
-  // build_list, append the ones this thread marked first to the compact list
-  // with one counter update per wave
-  uint32_t fresh = 0;  // bit k: node k newly marked by this thread
+  // order, where neighbouring particles' nodes share cache lines); the
+  // fused organisation's list of touched nodes is then compacted from the
+  // mask in site order (k_compact)
   if (valid && !A.mark_in_couple)
-    for (int k = 0; k < 8; ++k) {
-      const uint32_t bit = 1u << (node[k] & 31);
-      if (A.build_list) {
-        const uint32_t old = atomicOr(&mask[node[k] >> 5], bit);
-        if (!(old & bit)) fresh |= 1u << k;
-      } else {
-        atomicOr(&mask[node[k] >> 5], bit);
-      }
-    }
-  if (A.build_list) {
-    // exclusive prefix of the fresh counts over the wave
-    const int mine = __popc(fresh);
-    int incl = mine;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int t = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += t;
-    }
-    const int total = __shfl(incl, 63, 64);
-    int base = 0;
-    if (lane == 63 && total > 0) base = atomicAdd(nlist, total);
-    base = __shfl(base, 63, 64);
-    int slot = base + incl - mine;
-    for (int k = 0; k < 8; ++k)
-      if (fresh & (1u << k)) list[slot++] = int32_t(node[k]);
-  }
+    for (int k = 0; k < 8; ++k) atomicOr(&mask[node[k] >> 5], 1u << (node[k] & 31));
   for (int a = 0; a < 3; ++a) mom[a] = wave_sum(mom[a]);
   if (lane == 0)
     for (int a = 0; a < 3; ++a) part[wv][a] = mom[a];
@@ -151,10 +124,49 @@ __device__ __forceinline__ void begin_block(const PartArgs& A, double* __restric
 __global__ __launch_bounds__(256) void k_begin(PartArgs A, double* __restrict__ x, double* __restrict__ v,
                                                const double* __restrict__ F, const double* __restrict__ Fc,
                                                const int32_t* __restrict__ type, uint32_t* __restrict__ mask,
-                                               int32_t* __restrict__ list, int32_t* __restrict__ nlist,
                                                int32_t* __restrict__ cell_count, int32_t* __restrict__ cell_of,
                                                int32_t* __restrict__ rank_of, double* __restrict__ red) {
-  begin_block(A, x, v, F, Fc, type, mask, list, nlist, cell_count, cell_of, rank_of, red, blockIdx.x);
+  begin_block(A, x, v, F, Fc, type, mask, cell_count, cell_of, rank_of, red, blockIdx.x);
+}
+
+// The touched-node list of the fused organisation from the mask: block blk
+// takes 256 mask words (8,192 sites), scans their bit counts and reserves
+// its place in the list with one counter update, then each thread writes
+// its word's marked sites in increasing order.  The list is in site order
+// within each block's range (the order of the ranges follows the counter
+// updates; the re-collision of a node does not depend on it), so that the
+// re-collision's consecutive threads pull from neighbouring sites.
+constexpr int COMPACT_WORDS = 256;
+__device__ __forceinline__ void compact_block(const uint32_t* __restrict__ mask, int64_t words,
+                                              int32_t* __restrict__ list, int32_t* __restrict__ nlist, int64_t blk) {
+  __shared__ int wsum[COMPACT_WORDS / 64];
+  __shared__ int base;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t w = blk * COMPACT_WORDS + threadIdx.x;
+  const uint32_t m = w < words ? mask[w] : 0u;
+  const int mine = __popc(m);
+  int incl = mine;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int i = 0; i < COMPACT_WORDS / 64; ++i) tot += wsum[i];
+    base = tot > 0 ? atomicAdd(nlist, tot) : 0;
+  }
+  __syncthreads();
+  int slot = base + incl - mine;
+  for (int i = 0; i < wv; ++i) slot += wsum[i];
+  for (uint32_t b = m; b != 0u; b &= b - 1u) list[slot++] = int32_t(w * 32 + (__ffs(b) - 1));
+}
+
+__global__ __launch_bounds__(COMPACT_WORDS) void k_compact(const uint32_t* __restrict__ mask, int64_t words,
+                                                           int32_t* __restrict__ list, int32_t* __restrict__ nlist) {
+  compact_block(mask, words, list, nlist, blockIdx.x);
 }
 
 // exclusive scan of cell counts: per-1024 block, then block totals, then add
@@ -731,7 +743,12 @@ hipError_t particles_begin(lbmd_ctx* h) {
   const int64_t nb = (h->np + 255) / 256;
   h->red_part_used = nb;
   hipLaunchKernelGGL(k_begin, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, h->type, h->mask,
-                     h->flag_list, h->nflag, h->cell_count, h->cell_of, h->rank_of, h->red_part);
+                     h->cell_count, h->cell_of, h->rank_of, h->red_part);
+  if (A.build_list) {
+    const int64_t words = (h->N + 31) / 32;
+    hipLaunchKernelGGL(k_compact, dim3((words + COMPACT_WORDS - 1) / COMPACT_WORDS), dim3(COMPACT_WORDS), 0,
+                       h->stream, h->mask, words, h->flag_list, h->nflag);
+  }
   if (A.use_cells) {
     const int64_t n = h->ncells;
     const int64_t nblk = (n + 1023) / 1024;
@@ -834,8 +851,25 @@ __global__ __launch_bounds__(256) void k_begin_batch(const BatchJob* __restrict_
     const bool a = act != 0;
     __syncthreads();
     if (a)
-      begin_block(J.A, J.x, J.v, J.F, J.Fc, J.type, J.mask, J.flag_list, J.nflag, nullptr, nullptr, nullptr,
-                  J.red_part, u - J.pblk_begin);
+      begin_block(J.A, J.x, J.v, J.F, J.Fc, J.type, J.mask, nullptr, nullptr, nullptr, J.red_part,
+                  u - J.pblk_begin);
+    __syncthreads();
+  }
+}
+
+// Each block walks blocks of 256 mask words of the flattened mask range.
+__global__ __launch_bounds__(COMPACT_WORDS) void k_compact_batch(const BatchJob* __restrict__ jobs,
+                                                                 const BatchHeader* __restrict__ hdr) {
+  __shared__ int act;
+  const int nj = hdr->njobs;
+  const int64_t total = hdr->ncmpblk;
+  for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const BatchJob& J = jobs[batch_job_of<&BatchJob::cmp_begin>(jobs, nj, u)];
+    if (threadIdx.x == 0) act = batch_active(J) ? 1 : 0;
+    __syncthreads();
+    const bool a = act != 0;
+    __syncthreads();
+    if (a) compact_block(J.mask, J.words, J.flag_list, J.nflag, u - J.cmp_begin);
     __syncthreads();
   }
 }
@@ -867,6 +901,7 @@ constexpr int BATCH_PART_GRID = 1024;
 
 hipError_t batch_particles_begin(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr) {
   hipLaunchKernelGGL(k_begin_batch, dim3(BATCH_PART_GRID), dim3(256), 0, st, jobs, hdr);
+  hipLaunchKernelGGL(k_compact_batch, dim3(BATCH_PART_GRID), dim3(COMPACT_WORDS), 0, st, jobs, hdr);
   return hipGetLastError();
 }
 hipError_t batch_particles_couple(hipStream_t st, const BatchJob* jobs, const BatchHeader* hdr) {
@@ -879,7 +914,7 @@ hipError_t batch_particles_end(hipStream_t st, const BatchJob* jobs, const Batch
 }
 
 // Particle arguments of a batch job: no pair potentials (no cell list), the
-// touched nodes appended to the compact list for the re-collision.
+// touched nodes compacted into the list for the re-collision.
 void batch_fill_particles(const lbmd_ctx* h, BatchJob& J) {
   J.A = args(h);
   J.A.use_cells = 0;
@@ -892,6 +927,8 @@ void batch_fill_particles(const lbmd_ctx* h, BatchJob& J) {
   J.type = h->type;
   J.red_part = h->red_part;
   J.npblk = (h->np + 255) / 256;
+  J.words = (h->N + 31) / 32;
+  J.ncmpblk = (J.words + COMPACT_WORDS - 1) / COMPACT_WORDS;
 }
 
 }  // namespace lbmd
