@@ -262,19 +262,19 @@ __device__ __forceinline__ double group8_sum(double v) {
   return v;
 }
 
-// Pair and bond forces, eight lanes per particle in cell order.  The cells
+// Pair and bond forces, LANES (1 or 8) lanes per particle in cell order.  The cells
 // of one x row are consecutive in the sorted order, so each (y, z) row of
 // neighbour cells is one contiguous run of xs (two where the row wraps in
 // x); rows and columns of cells whose nearest face lies beyond the cut-off
 // from the particle are skipped (the face distance is measured in FP64 with
-// a margin, so no pair inside the cut-off is lost).  The eight lanes look
-// up all run bounds together (one round trip to memory) into an LDS table,
-// then take consecutive candidates of each run together (one 256-byte piece
-// of xs per round) in one rolled loop over the runs, which keeps the kernel
-// at 94 registers.  Each pair term is evaluated as in a one-lane loop; the
-// lanes' partial sums are added by the 8-lane butterfly.
+// a margin, so no pair inside the cut-off is lost).  The lanes look up all
+// run bounds together (one round trip to memory) into an LDS table, then
+// take consecutive candidates of each run together (with eight lanes, one
+// 256-byte piece of xs per round) in one rolled loop over the runs, which
+// keeps the kernel at 94 registers.  Each pair term is evaluated as in a
+// one-lane loop; eight lanes' partial sums are added by the 8-lane
+// butterfly.
 constexpr int PAIRS_BLOCK = 256;
-constexpr int PAIRS_PER_BLOCK = PAIRS_BLOCK / 8;
 
 // -dU/dr / r of the pair potentials at squared distance r2 (0 beyond both
 // cut-offs); qq = q_p q_j
@@ -298,6 +298,7 @@ __device__ __forceinline__ double pair_fr_over_r(const PartArgs& A, double r2, d
   return fr_over_r;
 }
 
+template <int LANES>
 __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double* __restrict__ x,
                                                        const int32_t* __restrict__ type,
                                                        const int32_t* __restrict__ cell_start,
@@ -307,10 +308,12 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
                                                        const int32_t* __restrict__ bstart,
                                                        const int32_t* __restrict__ bnbr, double* __restrict__ Fcons) {
   // per group: the [begin, end) of the up to 18 runs of xs it scans
-  __shared__ int2 runs[PAIRS_PER_BLOCK][18];
-  const int grp = int(threadIdx.x >> 3), lane = int(threadIdx.x & 7);
+  static_assert(LANES == 1 || LANES == 8, "one or eight lanes per particle");
+  constexpr int PER_BLOCK = PAIRS_BLOCK / LANES;
+  __shared__ int2 runs[PER_BLOCK][18];
+  const int grp = int(threadIdx.x / LANES), lane = int(threadIdx.x % LANES);
   // sorted position of the group's particle
-  const int64_t k = int64_t(blockIdx.x) * PAIRS_PER_BLOCK + grp;
+  const int64_t k = int64_t(blockIdx.x) * PER_BLOCK + grp;
   const bool live = k < A.np;
   const int64_t p = !live ? 0 : (A.use_cells ? int64_t(perm[k]) : k);
   const double xp[3] = {live ? x[3 * p] : 0.0, live ? x[3 * p + 1] : 0.0, live ? x[3 * p + 2] : 0.0};
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
     }
     // the lanes look up the rows' run bounds together (lane l: rows l and
     // l + 8), one round trip to memory
-    for (int i = lane; i < 9; i += 8) {
+    for (int i = lane; i < 9; i += LANES) {
       const int dz = i / 3 - 1, dy = i % 3 - 1;
       const bool on = live && dz >= lo[2] && dz <= hi[2] && dy >= lo[1] && dy <= hi[1];
       const int row = (wrapi(cc[2] + dz, nc2) * nc1 + wrapi(cc[1] + dy, nc1)) * nc0;
@@ -378,7 +381,7 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
 #pragma unroll 1
       for (int r = 0; r < 18; ++r) {
         const int2 rr = runs[grp][r];
-        for (int jj = rr.x + lane; jj < rr.y; jj += 8) {
+        for (int jj = rr.x + lane; jj < rr.y; jj += LANES) {
           if (jj == k) continue;
           const double4 q = *reinterpret_cast<const double4*>(xs + 4 * int64_t(jj));
           double d[3] = {q.x - xp[0], q.y - xp[1], q.z - xp[2]};
@@ -397,7 +400,7 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
   }
   if (!live) return;  // whole groups, after the block's barrier
   if (A.pp.fene_on && bstart) {
-    for (int jj = bstart[p] + lane; jj < bstart[p + 1]; jj += 8) {
+    for (int jj = bstart[p] + lane; jj < bstart[p + 1]; jj += LANES) {
       const int q = bnbr[jj];
       double d[3];
       for (int a = 0; a < 3; ++a) d[a] = min_image(x[3 * q + a] - xp[a], L[a]);
@@ -408,8 +411,12 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
       add_radial(fr_over_r, d, Fp);
     }
   }
-  const double F0 = group8_sum(Fp[0]), F1 = group8_sum(Fp[1]), F2 = group8_sum(Fp[2]);
-  if (lane < 3) Fcons[3 * p + lane] = lane == 0 ? F0 : (lane == 1 ? F1 : F2);
+  if (LANES == 1) {
+    for (int a = 0; a < 3; ++a) Fcons[3 * p + a] = Fp[a];
+  } else {
+    const double F0 = group8_sum(Fp[0]), F1 = group8_sum(Fp[1]), F2 = group8_sum(Fp[2]);
+    if (lane < 3) Fcons[3 * p + lane] = lane == 0 ? F0 : (lane == 1 ? F1 : F2);
+  }
 }
 
 // Coupling force: trilinear interpolation of u_c and the lattice density
@@ -781,9 +788,18 @@ hipError_t particles_pairs(lbmd_ctx* h) {
   if (!has_conservative(h)) return hipSuccess;
   PartArgs A = args(h);
   if (hipError_t e = hipStreamWaitEvent(h->side, h->ev_sorted, 0)) return e;
-  const int64_t nb = (h->np + PAIRS_PER_BLOCK - 1) / PAIRS_PER_BLOCK;
-  hipLaunchKernelGGL(k_pairs, dim3(nb), dim3(PAIRS_BLOCK), 0, h->side, A, h->x, h->type, h->cell_start, h->cell_perm,
-                     h->cell_of, h->xs, h->bond_start, h->bond_nbr, h->Fcons);
+  // eight lanes per particle where a particle has many candidates (about 6
+  // or more on average over the scanned cells), one where it has few: there
+  // the eight-lane grid would take slots from the coupling kernel beside it
+  const double cand = h->ncells > 0 ? 27.0 * double(h->np) / double(h->ncells) : 0.0;
+  if (cand >= 6.0)
+    hipLaunchKernelGGL(k_pairs<8>, dim3((h->np + PAIRS_BLOCK / 8 - 1) / (PAIRS_BLOCK / 8)), dim3(PAIRS_BLOCK), 0,
+                       h->side, A, h->x, h->type, h->cell_start, h->cell_perm, h->cell_of, h->xs, h->bond_start,
+                       h->bond_nbr, h->Fcons);
+  else
+    hipLaunchKernelGGL(k_pairs<1>, dim3((h->np + PAIRS_BLOCK - 1) / PAIRS_BLOCK), dim3(PAIRS_BLOCK), 0, h->side, A,
+                       h->x, h->type, h->cell_start, h->cell_perm, h->cell_of, h->xs, h->bond_start, h->bond_nbr,
+                       h->Fcons);
   if (hipError_t e = hipGetLastError()) return e;
   return hipEventRecord(h->ev_pairs, h->side);
 }
