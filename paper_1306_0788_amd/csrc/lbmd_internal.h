@@ -225,6 +225,7 @@ struct PartArgs {
   int use_cells;  // particles sorted by cell (perm, xs) this step
   int build_list;  // compact the touched nodes into a list after the marks (fused organisation)
   int mark_in_couple;  // the coupling kernel marks the touched nodes (push organisation)
+  int mark_in_begin;   // the half kick marks them (no cell list: batches)
 };
 
 // Scalar parameters of one fluid step, passed by value to the kernels.

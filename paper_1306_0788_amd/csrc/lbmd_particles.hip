@@ -100,18 +100,19 @@ __device__ __forceinline__ void begin_block(const PartArgs& A, double* __restric
       xp[a] = wrapd(x[3 * p + a] + vn, L[a]);
       x[3 * p + a] = xp[a];
     }
-    if (!A.mark_in_couple) interp(xp, A.nx, A.ny, A.nz, node, W);
+    if (A.mark_in_begin) interp(xp, A.nx, A.ny, A.nz, node, W);
     if (A.use_cells) {
       const int c = cell_index(xp, A);
       cell_of[p] = c;
       rank_of[p] = atomicAdd(&cell_count[c], 1);
     }
   }
-  // mark the 8 nodes (push organisation: the coupling kernel does, in cell
-  // order, where neighbouring particles' nodes share cache lines); the
-  // fused organisation's list of touched nodes is then compacted from the
-  // mask in site order (k_compact)
-  if (valid && !A.mark_in_couple)
+  // mark the 8 nodes here only without a cell list (batches): otherwise they
+  // are marked in cell order, where neighbouring particles' nodes share
+  // cache lines (push organisation: by the coupling kernel; else by
+  // k_mark_sorted after the sort); the fused organisation's list of touched
+  // nodes is then compacted from the mask in site order (k_compact)
+  if (valid && A.mark_in_begin)
     for (int k = 0; k < 8; ++k) atomicOr(&mask[node[k] >> 5], 1u << (node[k] & 31));
   for (int a = 0; a < 3; ++a) mom[a] = wave_sum(mom[a]);
   if (lane == 0)
@@ -231,6 +232,19 @@ __global__ void k_scatter(const int32_t* __restrict__ cell_of, const int32_t* __
   xs[4 * k + 1] = x[3 * p + 1];
   xs[4 * k + 2] = x[3 * p + 2];
   xs[4 * k + 3] = T.charge[type[p]];
+}
+
+// marks the 8 nodes of each particle in cell order (two-pass and fused
+// organisations, which need the mask before the coupling kernel runs)
+__global__ void k_mark_sorted(const double* __restrict__ xs, int64_t np, int nx, int ny, int nz,
+                              uint32_t* __restrict__ mask) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  const double xp[3] = {xs[4 * k], xs[4 * k + 1], xs[4 * k + 2]};
+  int64_t node[8];
+  double W[8];
+  interp(xp, nx, ny, nz, node, W);
+  for (int j = 0; j < 8; ++j) atomicOr(&mask[node[j] >> 5], 1u << (node[j] & 31));
 }
 
 __device__ __forceinline__ void add_radial(double fr_over_r, const double (&d)[3], double (&Fp)[3]) {
@@ -742,6 +756,7 @@ static PartArgs args(const lbmd_ctx* h) {
   A.use_cells = h->np > 0 && h->cell_start ? 1 : 0;  // particles sorted by cell (always, when there are any)
   A.build_list = organisation_of(h) == LBMD_KERNEL_FUSED ? 1 : 0;
   A.mark_in_couple = organisation_of(h) == LBMD_KERNEL_PUSH ? 1 : 0;
+  A.mark_in_begin = !A.mark_in_couple && !A.use_cells ? 1 : 0;
   return A;
 }
 
@@ -751,11 +766,6 @@ hipError_t particles_begin(lbmd_ctx* h) {
   h->red_part_used = nb;
   hipLaunchKernelGGL(k_begin, dim3(nb), dim3(256), 0, h->stream, A, h->x, h->v, h->F, h->Fc, h->type, h->mask,
                      h->cell_count, h->cell_of, h->rank_of, h->red_part);
-  if (A.build_list) {
-    const int64_t words = (h->N + 31) / 32;
-    hipLaunchKernelGGL(k_compact, dim3((words + COMPACT_WORDS - 1) / COMPACT_WORDS), dim3(COMPACT_WORDS), 0,
-                       h->stream, h->mask, words, h->flag_list, h->nflag);
-  }
   if (A.use_cells) {
     const int64_t n = h->ncells;
     const int64_t nblk = (n + 1023) / 1024;
@@ -766,6 +776,14 @@ hipError_t particles_begin(lbmd_ctx* h) {
                        h->scan_block, n + 1);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, h->stream, h->cell_of, h->rank_of, h->cell_start,
                        h->cell_perm, h->x, h->type, h->types, h->xs, h->np);
+    if (!A.mark_in_couple)
+      hipLaunchKernelGGL(k_mark_sorted, dim3(nb), dim3(256), 0, h->stream, h->xs, h->np, h->p.nx, h->p.ny, h->p.nz,
+                         h->mask);
+  }
+  if (A.build_list) {
+    const int64_t words = (h->N + 31) / 32;
+    hipLaunchKernelGGL(k_compact, dim3((words + COMPACT_WORDS - 1) / COMPACT_WORDS), dim3(COMPACT_WORDS), 0,
+                       h->stream, h->mask, words, h->flag_list, h->nflag);
   }
   return hipGetLastError();
 }
@@ -936,6 +954,7 @@ void batch_fill_particles(const lbmd_ctx* h, BatchJob& J) {
   J.A.use_cells = 0;
   J.A.build_list = 1;
   J.A.mark_in_couple = 0;
+  J.A.mark_in_begin = 1;
   J.x = h->x;
   J.v = h->v;
   J.F = h->F;
