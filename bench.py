@@ -332,7 +332,7 @@ def run_workload(name, stream, kernel, tiling, precision, autotune, cache, graph
     tuned = None
     if autotune:
         print("bench: autotuning the tiling", file=sys.stderr, flush=True)
-        tuned = sim.autotune(reps=3, cache_path=cache)
+        tuned = sim.autotune(reps=5, cache_path=cache)
     if graph:
         sim.set_graph(True)
     N = int(np.prod(w["shape"]))

@@ -338,8 +338,10 @@ int lbmd_set_graph(lbmd_handle h, int32_t enable);
 
 /* Tiling autotuner.  Times the fluid passes of the organisation the next
    step would use, reps times per candidate tiling (rows per tile, planes per
-   z chunk, HOLD and XCD flags; non-temporal stores on), on the current state
-   without advancing it, and keeps the fastest as if set by lbmd_set_tiling.
+   z chunk, HOLD and XCD flags; non-temporal stores on) in each of two sweeps
+   over the candidates, on the current state without advancing it, and keeps
+   the fastest (each candidate timed by the better of its two sweeps) as if
+   set by lbmd_set_tiling.
    cache_path (may be NULL): a text file of "nx ny nz precision organisation
    forcing noise tile_y tile_z flags ms" lines; an existing entry for the
    same key is applied without timing, a new result is appended.  chosen

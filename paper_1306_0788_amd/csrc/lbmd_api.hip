@@ -372,43 +372,36 @@ int autotune(lbmd_ctx* h, int reps, const char* cache_path, int32_t* chosen, dou
   double best = 1e300;
   Cand win = cands.front();
   int rc = LBMD_OK;
-  std::vector<double> times;
-  for (const Cand& c : cands) {
-    lbmd_set_tiling(h, c.ty, c.tz, c.flags);
-    hipError_t e = fluid_pass_a(h);
-    if (e == hipSuccess) e = fluid_pass_b(h);
-    if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) {
-      e = fluid_pass_a(h);
+  // two sweeps over the candidates, each candidate's time the smaller of
+  // its two, so that neither the order of the candidates nor one disturbed
+  // measurement decides between tilings a few percent apart
+  std::vector<double> times(cands.size(), 1e300);
+  for (int sweep = 0; sweep < 2 && rc == LBMD_OK; ++sweep)
+    for (size_t i = 0; i < cands.size(); ++i) {
+      const Cand& c = cands[i];
+      lbmd_set_tiling(h, c.ty, c.tz, c.flags);
+      hipError_t e = fluid_pass_a(h);
       if (e == hipSuccess) e = fluid_pass_b(h);
-    }
-    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) {
-      rc = hip_fail(h, e, "autotune");
-      break;
-    }
-    times.push_back(ms / reps);
-    if (ms / reps < best) {
-      best = ms / reps;
-      win = c;
-    }
-  }
-  // push organisation: among the candidates within 1 % of the best time,
-  // the one with the fewest rows per tile (tiles of 16 rows keep more live
-  // values than the registers hold, and the spill traffic makes the kernel
-  // move about 10 % more HBM bytes than at 4 rows for the same time)
-  if (rc == LBMD_OK && org == LBMD_KERNEL_PUSH) {
-    const double fastest = best;
-    for (size_t i = 0; i < cands.size(); ++i)
-      if (times[i] <= 1.01 * fastest &&
-          (cands[i].ty < win.ty || (cands[i].ty == win.ty && times[i] < best))) {
-        win = cands[i];
-        best = times[i];
+      if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        e = fluid_pass_a(h);
+        if (e == hipSuccess) e = fluid_pass_b(h);
       }
-  }
+      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = hip_fail(h, e, "autotune");
+        break;
+      }
+      times[i] = std::min(times[i], double(ms) / reps);
+    }
+  for (size_t i = 0; rc == LBMD_OK && i < cands.size(); ++i)
+    if (times[i] < best) {
+      best = times[i];
+      win = cands[i];
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->prof_on = prof;
