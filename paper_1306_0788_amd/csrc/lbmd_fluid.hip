@@ -373,8 +373,10 @@ __global__ __launch_bounds__(256) void k_fix(const S* __restrict__ src, S* __res
 // conservation sums and the status; at the nodes particles touch, the raw
 // momentum and the two densities go to the node record (the coupling kernel
 // forms the neighbour sums there from the density field).  A plain
-// streaming read of the 38 pulled populations per site.
-constexpr int DENS_BLOCK = 512, DENS_GRID = 2048;
+// streaming read of the 38 pulled populations per site.  512 blocks of 512
+// threads (half the chip's wave slots) still stream at the full rate and
+// leave the other half to the pair forces beside the pass.
+constexpr int DENS_BLOCK = 512, DENS_GRID = 512;
 template <class S>
 __global__ __launch_bounds__(DENS_BLOCK) void k_dens(const S* __restrict__ src_, arith_t<S>* __restrict__ rho,
                                                      FluidConsts<arith_t<S>> K, const uint32_t* __restrict__ mask,
