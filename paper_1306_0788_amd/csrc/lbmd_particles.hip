@@ -585,7 +585,9 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
     // the cube's two density planes in LDS (16 loads each instead of 38),
     // then each lane takes its node's 18 neighbours from it: the same sites
     // and summation order as reading them one by one.
-    __shared__ C cube[COUPLE8_BLOCK / 8][2][64];
+    // one padding word per group, so that the 8 groups' cubes do not start
+    // on the same LDS bank
+    __shared__ C cube[COUPLE8_BLOCK / 8][2 * 64 + 1];
     const int grp = int(threadIdx.x >> 3);
     {
       const int X0 = cell_coord(fl[0], A.nx), Y0 = cell_coord(fl[1], A.ny), Z0 = cell_coord(fl[2], A.nz);
@@ -595,12 +597,12 @@ __global__ __launch_bounds__(COUPLE8_BLOCK) void k_couple8(PartArgs A, const dou
       for (int m = 0; m < 16; ++m) {
         const int e = k + 8 * m;  // component e / 64, cube site e % 64 (x fastest)
         const int c = e >> 6, cs = e & 63;
-        cube[grp][c][cs] = dens(c, wrap2(X0 - 1 + (cs & 3), A.nx), wrap2(Y0 - 1 + ((cs >> 2) & 3), A.ny),
+        cube[grp][c * 64 + cs] = dens(c, wrap2(X0 - 1 + (cs & 3), A.nx), wrap2(Y0 - 1 + ((cs >> 2) & 3), A.ny),
                                 wrap2(Z0 - 1 + (cs >> 4), A.nz));
       }
     }
     __syncthreads();
-    auto cub = [&](int c, int i, int j, int l) -> C { return cube[grp][c][(l << 4) | (j << 2) | i]; };
+    auto cub = [&](int c, int i, int j, int l) -> C { return cube[grp][c * 64 + ((l << 4) | (j << 2) | i)]; };
 #pragma unroll
     for (int a = 0; a < 3; ++a) NA[a] = NB[a] = C(0);
 #pragma unroll
