@@ -344,13 +344,16 @@ int autotune(lbmd_ctx* h, int reps, const char* cache_path, int32_t* chosen, dou
   };
   std::vector<Cand> cands;
   const bool fused = org == LBMD_KERNEL_FUSED;
+  // short z chunks give a small lattice enough blocks for the chip (32^3 at
+  // 4 rows x 16 planes is 16 blocks); long ones spread the three-plane start
+  // of a march over more planes on a large lattice
   const int tys_f[] = {2, 4, 8}, tys_t[] = {4, 8, 16};
-  const int tzs_f[] = {8, 16, 32}, tzs_t[] = {16, 32, 64, 128};
+  const int tzs_f[] = {4, 8, 16, 32}, tzs_t[] = {4, 8, 16, 32, 64, 128};
   for (int a = 0; a < 3; ++a) {
     const int ty = fused ? tys_f[a] : tys_t[a];
     if (ty > std::max(2, h->p.ny) && ty != 2) continue;
     if (org == LBMD_KERNEL_PUSH && ty > push_rows_max(h)) continue;
-    const int ntz = fused ? 3 : 4;
+    const int ntz = fused ? 4 : 6;
     for (int b = 0; b < ntz; ++b) {
       const int tz = std::min(fused ? tzs_f[b] : tzs_t[b], h->p.nz);
       for (int xcd = 0; xcd < 2; ++xcd)
