@@ -150,9 +150,11 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
     const uint64_t p0 = uint64_t(0xD2511F53u) * c.x;
     const uint64_t p1 = uint64_t(0xCD9E8D57u) * c.z;
     U4 n;
-    n.x = uint32_t(p1 >> 32) ^ c.y ^ k0;
+    // three-input exclusive or in one instruction (truth table 0x96: set
+    // where an odd number of the inputs is set)
+    n.x = __builtin_amdgcn_bitop3_b32(uint32_t(p1 >> 32), c.y, k0, 0x96);
     n.y = uint32_t(p1);
-    n.z = uint32_t(p0 >> 32) ^ c.w ^ k1;
+    n.z = __builtin_amdgcn_bitop3_b32(uint32_t(p0 >> 32), c.w, k1, 0x96);
     n.w = uint32_t(p0);
     c = n;
     k0 += 0x9E3779B9u;
