@@ -529,22 +529,23 @@ __global__ __launch_bounds__(256) void k_pull_copy(const S* __restrict__ src_, S
 // final reductions: fluid partials [nf][5], particle partials [np][3] -> out[8]
 __device__ __forceinline__ void finalize_sums(const double* __restrict__ rf, int64_t nf, const double* __restrict__ rp,
                                               int64_t npb, double* __restrict__ out, int32_t* nflag, int64_t* step) {
-  __shared__ double sh[256];
-  for (int q = 0; q < 8; ++q) {
-    double s = 0;
-    if (q < 5)
-      for (int64_t b = threadIdx.x; b < nf; b += 256) s += rf[5 * b + q];
-    else
-      for (int64_t b = threadIdx.x; b < npb; b += 256) s += rp[3 * b + (q - 5)];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[q] = sh[0];
-    __syncthreads();
-  }
+  // one pass over the partials (5 fluid and 3 particle sums per thread),
+  // wave sums by shuffles, then the 4 waves' sums through LDS
+  __shared__ double sh[8][4];
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nf; b += 256)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) s[q] += rf[5 * b + q];
+  for (int64_t b = threadIdx.x; b < npb; b += 256)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) s[5 + q] += rp[3 * b + q];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s[q] = wave_sum(s[q]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sh[q][threadIdx.x >> 6] = s[q];
+  __syncthreads();
+  if (threadIdx.x < 8) out[threadIdx.x] = (sh[threadIdx.x][0] + sh[threadIdx.x][1]) + (sh[threadIdx.x][2] + sh[threadIdx.x][3]);
   if (threadIdx.x == 0) {
     *nflag = 0;
     *step += 1;
