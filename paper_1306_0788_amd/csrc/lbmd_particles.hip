@@ -170,41 +170,54 @@ __global__ __launch_bounds__(COMPACT_WORDS) void k_compact(const uint32_t* __res
   compact_block(mask, words, list, nlist, blockIdx.x);
 }
 
-// exclusive scan of cell counts: per-1024 block, then block totals, then add
+// exclusive scan of cell counts: per-1024 block, then block totals, then add.
+// Within a block: inclusive scans of the 16 waves by shuffles, then a scan
+// of the 16 wave totals by the first wave (two barriers in all).
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = int(threadIdx.x & 63);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+// exclusive prefix of v over the 1024 threads of the block; *total = sum
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+  __shared__ int wsum[16];
+  const int lane = int(threadIdx.x & 63), wv = int(threadIdx.x >> 6);
+  const int incl = wave_incl_scan(v);
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (wv == 0) {
+    const int w = wave_incl_scan(lane < 16 ? wsum[lane] : 0);
+    if (lane < 16) wsum[lane] = w;
+  }
+  __syncthreads();
+  const int r = (wv > 0 ? wsum[wv - 1] : 0) + incl - v;
+  *total = wsum[15];
+  __syncthreads();  // wsum is reused by the next call
+  return r;
+}
+
 __global__ __launch_bounds__(1024) void k_scan_blocks(const int32_t* __restrict__ cnt, int32_t* __restrict__ start,
                                                       int32_t* __restrict__ btot, int64_t n) {
-  __shared__ int32_t s[1024];
   const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
   const int32_t v = i < n ? cnt[i] : 0;
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-    __syncthreads();
-    s[threadIdx.x] += t;
-    __syncthreads();
-  }
-  if (i < n) start[i] = s[threadIdx.x] - v;
-  if (threadIdx.x == 1023) btot[blockIdx.x] = s[1023];
+  int tot;
+  const int ex = block_excl_scan(v, &tot);
+  if (i < n) start[i] = ex;
+  if (threadIdx.x == 0) btot[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ btot, int64_t nb) {
-  __shared__ int32_t s[1024];
   int32_t carry = 0;
   for (int64_t base = 0; base < nb; base += 1024) {
     const int64_t i = base + threadIdx.x;
     const int32_t v = i < nb ? btot[i] : 0;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-      __syncthreads();
-      s[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < nb) btot[i] = carry + s[threadIdx.x] - v;
-    const int32_t tot = s[1023];
-    __syncthreads();
+    int tot;
+    const int ex = block_excl_scan(v, &tot);
+    if (i < nb) btot[i] = carry + ex;
     carry += tot;
   }
 }
