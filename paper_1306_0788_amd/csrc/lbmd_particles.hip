@@ -222,24 +222,25 @@ __global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ btot, i
   }
 }
 
-__global__ void k_scan_add(int32_t* __restrict__ start, int32_t* __restrict__ cnt, const int32_t* __restrict__ btot,
-                           int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) {
-    start[i] += btot[i / 1024];
-    cnt[i] = 0;
-  }
-}
-
 // cell-sorted order: perm[k] = particle at sorted position k, and xs[k] =
 // its position and charge, so that a neighbour cell's particles are read as
 // one contiguous run
+// (the start of cell c is start[c] + btot[c / 1024]: the per-block scan
+// plus its block's offset; the cell counts are cleared here for the next
+// step, every non-zero count belonging to a cell that holds a particle)
+__device__ __forceinline__ int32_t cell_begin(const int32_t* __restrict__ start, const int32_t* __restrict__ btot,
+                                              int c) {
+  return start[c] + btot[c >> 10];
+}
 __global__ void k_scatter(const int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank_of,
-                          const int32_t* __restrict__ start, int32_t* __restrict__ perm, const double* __restrict__ x,
+                          const int32_t* __restrict__ start, const int32_t* __restrict__ btot,
+                          int32_t* __restrict__ cnt, int32_t* __restrict__ perm, const double* __restrict__ x,
                           const int32_t* __restrict__ type, ParticleTypes T, double* __restrict__ xs, int64_t np) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= np) return;
-  const int64_t k = start[cell_of[p]] + rank_of[p];
+  const int c = cell_of[p];
+  const int64_t k = cell_begin(start, btot, c) + rank_of[p];
+  cnt[c] = 0;
   perm[k] = int32_t(p);
   xs[4 * k] = x[3 * p];
   xs[4 * k + 1] = x[3 * p + 1];
@@ -329,6 +330,7 @@ template <int LANES>
 __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double* __restrict__ x,
                                                        const int32_t* __restrict__ type,
                                                        const int32_t* __restrict__ cell_start,
+                                                       const int32_t* __restrict__ btot,
                                                        const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ cell_of,
                                                        const double* __restrict__ xs,
@@ -391,9 +393,12 @@ __global__ __launch_bounds__(PAIRS_BLOCK) void k_pairs(PartArgs A, const double*
       const int dz = i / 3 - 1, dy = i % 3 - 1;
       const bool on = live && dz >= lo[2] && dz <= hi[2] && dy >= lo[1] && dy <= hi[1];
       const int row = (wrapi(cc[2] + dz, nc2) * nc1 + wrapi(cc[1] + dy, nc1)) * nc0;
-      runs[grp][2 * i] = on ? make_int2(cell_start[row + ra0], cell_start[row + ra1]) : make_int2(0, 0);
-      runs[grp][2 * i + 1] =
-          on && rb1 > rb0 ? make_int2(cell_start[row + rb0], cell_start[row + rb1]) : make_int2(0, 0);
+      runs[grp][2 * i] =
+          on ? make_int2(cell_begin(cell_start, btot, row + ra0), cell_begin(cell_start, btot, row + ra1))
+             : make_int2(0, 0);
+      runs[grp][2 * i + 1] = on && rb1 > rb0 ? make_int2(cell_begin(cell_start, btot, row + rb0),
+                                                         cell_begin(cell_start, btot, row + rb1))
+                                             : make_int2(0, 0);
     }
     __syncthreads();
     const double qp = live ? A.T.charge[type[p]] : 0.0;
@@ -787,10 +792,8 @@ hipError_t particles_begin(lbmd_ctx* h) {
     hipLaunchKernelGGL(k_scan_blocks, dim3(nblk), dim3(1024), 0, h->stream, h->cell_count, h->cell_start,
                        h->scan_block, n + 1);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, h->stream, h->scan_block, (n + 1 + 1023) / 1024);
-    hipLaunchKernelGGL(k_scan_add, dim3((n + 1 + 255) / 256), dim3(256), 0, h->stream, h->cell_start, h->cell_count,
-                       h->scan_block, n + 1);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, h->stream, h->cell_of, h->rank_of, h->cell_start,
-                       h->cell_perm, h->x, h->type, h->types, h->xs, h->np);
+                       h->scan_block, h->cell_count, h->cell_perm, h->x, h->type, h->types, h->xs, h->np);
     if (!A.mark_in_couple)
       hipLaunchKernelGGL(k_mark_sorted, dim3(nb), dim3(256), 0, h->stream, h->xs, h->np, h->p.nx, h->p.ny, h->p.nz,
                          h->mask);
@@ -827,12 +830,12 @@ hipError_t particles_pairs(lbmd_ctx* h) {
   const double cand = h->ncells > 0 ? 27.0 * double(h->np) / double(h->ncells) : 0.0;
   if (cand >= 6.0)
     hipLaunchKernelGGL(k_pairs<8>, dim3((h->np + PAIRS_BLOCK / 8 - 1) / (PAIRS_BLOCK / 8)), dim3(PAIRS_BLOCK), 0,
-                       h->side, A, h->x, h->type, h->cell_start, h->cell_perm, h->cell_of, h->xs, h->bond_start,
-                       h->bond_nbr, h->Fcons);
+                       h->side, A, h->x, h->type, h->cell_start, h->scan_block, h->cell_perm, h->cell_of, h->xs,
+                       h->bond_start, h->bond_nbr, h->Fcons);
   else
     hipLaunchKernelGGL(k_pairs<1>, dim3((h->np + PAIRS_BLOCK - 1) / PAIRS_BLOCK), dim3(PAIRS_BLOCK), 0, h->side, A,
-                       h->x, h->type, h->cell_start, h->cell_perm, h->cell_of, h->xs, h->bond_start, h->bond_nbr,
-                       h->Fcons);
+                       h->x, h->type, h->cell_start, h->scan_block, h->cell_perm, h->cell_of, h->xs, h->bond_start,
+                       h->bond_nbr, h->Fcons);
   if (hipError_t e = hipGetLastError()) return e;
   return hipEventRecord(h->ev_pairs, h->side);
 }
