@@ -390,10 +390,9 @@ def main():
                     help="population storage (default: the workload's); fp16dev / bf16dev store f - w rho0")
     ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("TILE_Y", "TILE_Z"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", dest="graph", action="store_true", default=True,
-                    help="advance the timed steps by replaying the step captured as a HIP graph (the default)")
-    ap.add_argument("--eager", dest="graph", action="store_false",
-                    help="advance the timed steps by launching every kernel from the host instead")
+    ap.add_argument("--graph", action="store_true",
+                    help="advance the timed steps by replaying the step captured as a HIP graph (the kernel's "
+                         "roofline time is then taken over eager warm-up steps, not the timed region)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the library's default tiling instead of running its autotuner before the "
                          "untimed warm-up")
