@@ -94,8 +94,9 @@ typedef struct lbmd_ctx* lbmd_handle;
                                  in-line                                      */
 #define LBMD_KERNEL_AUTO 2    /* fused with fewer than one touched node per 128
                                  sites; otherwise (and always with MRT) push
-                                 for a deterministic fluid and two-pass with
-                                 thermal noise                               */
+                                 for a deterministic fluid in FP32 or FP64,
+                                 two-pass with thermal noise or on 16-bit
+                                 storage                                     */
 #define LBMD_KERNEL_PUSH 3    /* one pass over the populations per step: the
                                  collide + stream pass also accumulates the
                                  next step's densities and momentum of every
@@ -175,7 +176,8 @@ int lbmd_set_particle_types(lbmd_handle h, int32_t ntypes, const double* kappa, 
    (-2, 0); BGK is every eigenvalue -1/tau), in place of the BGK relaxation
    with tau[].  Fluctuations (kT > 0) take each mode's own eigenvalue.  Needs
    LBMD_FORCE_PAPER; the step then uses the two-pass or the push
-   organisation (LBMD_KERNEL_AUTO: push without noise, two-pass with it; a
+   organisation (LBMD_KERNEL_AUTO: push without noise in FP32 or FP64,
+   two-pass with noise or on 16-bit storage; a
    kernel explicitly set to LBMD_KERNEL_FUSED is refused).  enable = 0
    returns to BGK.  Errors: LBMD_EINVAL, LBMD_ESTATE (in a batch). */
 int lbmd_set_mrt(lbmd_handle h, int32_t enable, double lambda_bulk, double lambda_shear, double lambda_mom,

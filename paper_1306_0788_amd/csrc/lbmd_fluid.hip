@@ -615,8 +615,13 @@ static int organisation(const lbmd_ctx* h) {
   // with thermal noise the push kernel's in-block gather comes on top of
   // the per-site normals; its collide pass then runs longer than the
   // density pass it saves (bead-spring chains at 256^3: 2.39 against
-  // 2.26 ms per step), so fluctuating steps use the two-pass organisation
-  const int many = h->p.kT > 0.0 ? LBMD_KERNEL_TWOPASS : LBMD_KERNEL_PUSH;
+  // 2.26 ms per step), so fluctuating steps use the two-pass organisation.
+  // On 16-bit storage the five 4-byte moments per site the push pass writes
+  // and reads weigh more against the 76 two-byte populations than the
+  // density pass it saves (256^3 with 160k particles: 13,600 against 11,500
+  // MLUPS binary16, 14,000 against 11,500 bfloat16), so those use it too.
+  const bool half = h->p.precision == LBMD_FP16DEV || h->p.precision == LBMD_BF16DEV;
+  const int many = h->p.kT > 0.0 || half ? LBMD_KERNEL_TWOPASS : LBMD_KERNEL_PUSH;
   // the MRT collision is built into the two-pass and push kernels only
   if (h->mrt)
     return h->p.kernel == LBMD_KERNEL_TWOPASS || h->p.kernel == LBMD_KERNEL_PUSH ? h->p.kernel : many;
