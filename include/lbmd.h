@@ -92,8 +92,8 @@ typedef struct lbmd_ctx* lbmd_handle;
                                  momentum at the touched nodes), then collide +
                                  stream with the particle force applied
                                  in-line                                      */
-#define LBMD_KERNEL_AUTO 2    /* fused with fewer than one touched node per 128
-                                 sites; otherwise (and always with MRT) push
+#define LBMD_KERNEL_AUTO 2    /* fused with fewer than one touched node per
+                                 2,048 sites; otherwise (and always with MRT) push
                                  for a deterministic fluid in FP32 or FP64,
                                  two-pass with thermal noise or on 16-bit
                                  storage                                     */

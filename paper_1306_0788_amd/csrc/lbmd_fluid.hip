@@ -628,8 +628,11 @@ static int organisation(const lbmd_ctx* h) {
   if (h->p.kernel != LBMD_KERNEL_AUTO) return h->p.kernel;
   // the fused pass re-collides every touched node with scattered accesses
   // (about 76 per node); the push pass writes and reads a five-value moment
-  // field per site.  Break-even near one touched node per 128 sites.
-  return (h->np == 0 || 8 * h->np * 128 < h->N) ? LBMD_KERNEL_FUSED : many;
+  // field per site.  At 256^3 FP32 the fused step is faster without
+  // particles (1.285 against 1.329 ms) and slower from 2,000 particles on
+  // (1.398 against 1.373 ms; 10,000: 1.491 against 1.393): break-even near
+  // one touched node per 2,048 sites.
+  return (h->np == 0 || 8 * h->np * 2048 < h->N) ? LBMD_KERNEL_FUSED : many;
 }
 
 struct Launch {
